@@ -1,0 +1,183 @@
+/*
+ * rn.h -- C ABI of librn, a gfx950 (MI355X) solver for steady flow through
+ * random resistor / pore networks (Dashtian & Sahimi, Sec. II).
+ *
+ * Problem (Sec. II, Eq. 3): a square (2D) or simple-cubic (3D) lattice of
+ * nodes joined by bonds of conductance g_ij >= 0 (g = 0: removed bond, the
+ * percolation dilution of Sec. V-VI). Mass balance sum_j g_ij (P_j - P_i) = 0
+ * holds at every interior node; the first node plane along the flow axis
+ * (inlet face) is held at P = 1, the last plane (outlet face) at P = 0, and
+ * no flow crosses the side faces. The library returns the total flux Q and
+ * Darcy's K (Eq. 4) = Q (n_axis - 1) / S, with S the product of the extents
+ * other than the flow axis (unit viscosity, bond length and pressure drop).
+ *
+ * Only interior nodes connected through occupied interior bonds to both
+ * faces carry flow (the "live" set). The solve is Jacobi-preconditioned
+ * conjugate gradients (Sec. II/IV) on the live set, either all in FP64 or
+ * with FP32 inner iterations and FP64 residual refreshes, FP64 solution
+ * accumulation and FP64 flux (the mixed-precision scheme of Sec. IV).
+ *
+ * Conventions
+ *   - Every call returns an int status: RN_OK (0) or a negative RN_E* code.
+ *     No C++ exception crosses the ABI.
+ *   - Lattice layout: node i = x + nx*(y + ny*z) (x fastest). g[k] is an
+ *     array of nx*ny*nz doubles; g[k][i] is the bond from node i to its
+ *     neighbour i + e_k (k = 0,1,2 for x,y,z). Entries whose neighbour lies
+ *     past the lattice edge are ignored (any value, even NaN). g[2] must be
+ *     NULL in 2D. Every other entry must be finite and >= 0 (RN_EINVAL
+ *     otherwise).
+ *   - Pointers in rn_problem live in the memory space named by its `mem`
+ *     field: RN_MEM_HOST (pageable or pinned host memory) or RN_MEM_DEVICE
+ *     (device memory on the context's GPU, e.g. a torch tensor's data_ptr).
+ *   - All caller buffers are borrowed for the duration of the call and never
+ *     freed by the library. Device memory the library needs belongs to the
+ *     rn_ctx and is bounded by its HBM budget.
+ *   - Calls on one rn_ctx are serialised by the caller (not thread-safe);
+ *     different contexts are independent.
+ */
+#ifndef RN_H
+#define RN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RN_OK 0
+#define RN_EINVAL (-1)    /* bad argument: dims, axis, NULL pointer, g < 0 / NaN / Inf, tol <= 0 */
+#define RN_ENOMEM (-2)    /* the request does not fit the context's HBM budget or device memory */
+#define RN_ENOCONV (-3)   /* max_iter reached; result holds the last iterate, converged = 0 */
+#define RN_ENUMERIC (-4)  /* CG breakdown (p.Ap <= 0 or a non-finite reduction) */
+#define RN_EDEVICE (-5)   /* a HIP runtime call failed; rn_last_error() has the message */
+#define RN_EAGAIN (-6)    /* rn_poll: the ticket is still running */
+#define RN_ENOTFOUND (-7) /* rn_poll: unknown or already collected ticket */
+
+/* rn_opts.precision */
+#define RN_FP64 0   /* FP64 CG throughout */
+#define RN_MIXED 1  /* FP32 inner CG, FP64 residual refresh, solution and flux */
+
+/* rn_problem.mem */
+#define RN_MEM_HOST 0
+#define RN_MEM_DEVICE 1
+
+typedef struct rn_ctx rn_ctx;
+
+/* One network: lattice, flow axis, conductances, optional outputs. */
+typedef struct {
+    int32_t dim;        /* 2 or 3 */
+    int32_t axis;       /* flow axis: 0 = x, 1 = y, 2 = z (< dim); its extent must be >= 2 */
+    int64_t nx, ny, nz; /* extents >= 1; nz == 1 in 2D; nx*ny*nz < 2^31 */
+    const double *g[3]; /* bond conductances, layout above; g[2] == NULL in 2D */
+    double *p_out;      /* nullable, nx*ny*nz doubles: nodal pressures. Faces 1 / 0; live
+                           nodes the solution; dead interior nodes 1 if connected to the
+                           inlet only, else 0 */
+    uint8_t *mask_out;  /* nullable, nx*ny*nz bytes: connectivity mask (rn_build_mask) */
+    int32_t mem;        /* RN_MEM_HOST or RN_MEM_DEVICE for g, p_out and mask_out */
+    int32_t reserved;   /* must be 0 */
+} rn_problem;
+
+/* Solver options; rn_opts_default() fills the defaults. */
+typedef struct {
+    int32_t precision;  /* RN_FP64 (default) or RN_MIXED */
+    int32_t reserved;   /* must be 0 */
+    double tol;         /* stop when ||b - A x||_2 <= tol ||b||_2, the FP64 true residual on
+                           the live set (default 1e-8) */
+    int64_t max_iter;   /* cap on CG iterations, i.e. operator applications (default 10^7) */
+    double delta;       /* RN_MIXED: refresh the FP64 residual once the FP32 residual has
+                           fallen by this factor since the last refresh (0 = default 0.1) */
+} rn_opts;
+
+/* Outcome of one solve. */
+typedef struct {
+    int32_t status;     /* RN_OK, RN_ENOCONV or RN_ENUMERIC */
+    int32_t converged;  /* 1 when the true relative residual is <= tol */
+    double Q_in;        /* flux leaving the inlet face (plus direct inlet-outlet bonds) */
+    double Q_out;       /* flux entering the outlet face (plus direct bonds) */
+    double G;           /* conductance in energy form: Q_in - x.(b - A x) = sum g dP^2 */
+    double K;           /* Darcy K of Eq. 4: G (n_axis - 1) / S */
+    double rel_resid;   /* final ||b - A x|| / ||b|| in FP64 (0 when nothing is live) */
+    int64_t iters;      /* CG iterations */
+    int64_t refreshes;  /* FP64 true-residual refreshes (the first one computes b) */
+    int64_t n_live;     /* interior nodes connected to both faces */
+    int64_t passes;     /* kernel launches of the iteration loop (including idle ones) */
+    double t_mask_s;    /* device time: upload, validation and connectivity */
+    double t_loop_s;    /* device time: iteration loop (all passes) */
+    double t_total_s;   /* host wall time of the call */
+} rn_result;
+
+/* Library version, 100 * major + minor. */
+int rn_version(void);
+
+/* Human-readable name of a status code; never NULL. */
+const char *rn_strerror(int status);
+
+/* Fill *opts with the defaults above. RN_EINVAL if opts is NULL. */
+int rn_opts_default(rn_opts *opts);
+
+/*
+ * Create a context on HIP device `device` with an HBM budget of
+ * `hbm_budget_bytes` for the library's own buffers (0 = 90% of the device's
+ * free memory at creation). The context owns a non-blocking stream at default
+ * priority until rn_set_stream() replaces it. *out receives the handle.
+ * Errors: RN_EINVAL (NULL out, bad device), RN_EDEVICE.
+ */
+int rn_create(int device, size_t hbm_budget_bytes, rn_ctx **out);
+
+/* Release every device and host resource of the context. NULL is accepted. */
+int rn_destroy(rn_ctx *ctx);
+
+/*
+ * Launch all further work of this context on `stream` (a hipStream_t, e.g.
+ * torch.cuda.current_stream().cuda_stream); NULL restores the context's own
+ * stream. The caller keeps ownership of the stream and must keep it alive.
+ */
+int rn_set_stream(rn_ctx *ctx, void *stream);
+
+/* Message of the last RN_EDEVICE on this context ("" if none). */
+const char *rn_last_error(rn_ctx *ctx);
+
+/*
+ * Check a problem and options without touching a device: shapes, axis,
+ * pointers, reserved fields, options and, for RN_MEM_HOST, every in-lattice
+ * conductance (finite, >= 0). opts may be NULL (defaults). Returns RN_OK or
+ * RN_EINVAL; the same checks open rn_solve and rn_build_mask.
+ */
+int rn_validate(const rn_problem *prob, const rn_opts *opts);
+
+/*
+ * Device bytes one solve of `prob` with `opts` needs (opts NULL: defaults);
+ * 0 when the problem is invalid. Used for admission against the budget.
+ */
+size_t rn_footprint(const rn_problem *prob, const rn_opts *opts);
+
+/*
+ * Connectivity mask of a network (the "live set" definition above; Sec. V-VI
+ * dilution makes it non-trivial). Writes prob->mask_out (required), one byte
+ * per node: bit0 = the node's interior component has an occupied bond to an
+ * inlet-face node, bit1 = the same for the outlet face, bit2 = face node.
+ * Inlet-face nodes are 5, outlet-face nodes 6, live interior nodes 3, other
+ * interior nodes 0, 1 or 2. Paths run only through occupied interior-interior
+ * bonds. *n_live_out (nullable) receives the number of live nodes.
+ * Errors: RN_EINVAL, RN_ENOMEM, RN_EDEVICE; outputs untouched on error.
+ */
+int rn_build_mask(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
+
+/*
+ * Solve one network (Sec. II, Eqs. 3-4): mask, Jacobi-PCG from x = 0 on the
+ * live set to opts->tol, then fluxes, energy conductance and K, all reduced
+ * in FP64 on the device. Writes *out, and prob->p_out / prob->mask_out when
+ * non-NULL. A network with no live node returns RN_OK, converged = 1,
+ * iters = 0 and G = K = 0 except for direct inlet-outlet bonds (n_axis = 2).
+ * Returns out->status (RN_OK, RN_ENOCONV, RN_ENUMERIC) once the solve ran;
+ * RN_EINVAL / RN_ENOMEM / RN_EDEVICE before it (outputs untouched).
+ */
+int rn_solve(rn_ctx *ctx, const rn_problem *prob, const rn_opts *opts, rn_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RN_H */

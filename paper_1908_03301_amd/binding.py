@@ -1,0 +1,240 @@
+"""ctypes binding of librn (include/rn.h): argument marshalling only.
+
+Every step of the solve runs in librn's HIP kernels; this module converts
+numpy arrays (host memory) or torch CUDA tensors (device memory) into the C
+structures and calls the entry points of the same names. It raises
+``RuntimeError`` when librn.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librn.so")
+
+RN_OK, RN_EINVAL, RN_ENOMEM, RN_ENOCONV, RN_ENUMERIC, RN_EDEVICE, RN_EAGAIN, RN_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
+RN_FP64, RN_MIXED = 0, 1
+RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
+
+EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
+            "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve"]
+
+
+class rn_problem(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("axis", C.c_int32),
+                ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
+                ("g", C.c_void_p * 3), ("p_out", C.c_void_p), ("mask_out", C.c_void_p),
+                ("mem", C.c_int32), ("reserved", C.c_int32)]
+
+
+class rn_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int64), ("delta", C.c_double)]
+
+
+class rn_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("converged", C.c_int32),
+                ("Q_in", C.c_double), ("Q_out", C.c_double), ("G", C.c_double), ("K", C.c_double),
+                ("rel_resid", C.c_double), ("iters", C.c_int64), ("refreshes", C.c_int64),
+                ("n_live", C.c_int64), ("passes", C.c_int64),
+                ("t_mask_s", C.c_double), ("t_loop_s", C.c_double), ("t_total_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RNError(RuntimeError):
+    def __init__(self, code: int, msg: str = ""):
+        super().__init__(f"librn status {code} ({strerror(code)}){': ' + msg if msg else ''}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load librn.so (built in-tree by ``__graft_entry__.build()``); no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        P, I64 = C.POINTER, C.c_int64
+        L.rn_version.restype = C.c_int
+        L.rn_strerror.argtypes = [C.c_int]
+        L.rn_strerror.restype = C.c_char_p
+        L.rn_opts_default.argtypes = [P(rn_opts)]
+        L.rn_create.argtypes = [C.c_int, C.c_size_t, P(C.c_void_p)]
+        L.rn_destroy.argtypes = [C.c_void_p]
+        L.rn_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        L.rn_last_error.argtypes = [C.c_void_p]
+        L.rn_last_error.restype = C.c_char_p
+        L.rn_validate.argtypes = [P(rn_problem), P(rn_opts)]
+        L.rn_validate.restype = C.c_int
+        L.rn_footprint.argtypes = [P(rn_problem), P(rn_opts)]
+        L.rn_footprint.restype = C.c_size_t
+        L.rn_build_mask.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
+        L.rn_solve.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(rn_result)]
+        for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().rn_strerror(int(code)).decode()
+    except RuntimeError:
+        return str(code)
+
+
+def opts(precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000, delta: float = 0.0) -> rn_opts:
+    o = rn_opts()
+    lib().rn_opts_default(C.byref(o))
+    o.precision, o.tol, o.max_iter, o.delta = int(precision), float(tol), int(max_iter), float(delta)
+    return o
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+@dataclass
+class Problem:
+    """An rn_problem plus references that keep its buffers alive."""
+    c: rn_problem
+    keep: list
+
+
+def problem(net=None, *, dim=None, nx=None, ny=None, nz=1, axis=0, g: Optional[Sequence] = None,
+            p_out=None, mask_out=None) -> Problem:
+    """Build an rn_problem from a Network (inputs.Network) or explicit fields.
+
+    ``g`` entries are float64 numpy arrays (host) or float64 CUDA tensors
+    (device); ``p_out`` / ``mask_out`` must be in the same memory space.
+    """
+    if net is not None:
+        dim, nx, ny, nz, axis, g = net.dim, net.nx, net.ny, net.nz, net.axis, net.g
+    keep: List = []
+    pr = rn_problem()
+    pr.dim, pr.axis, pr.nx, pr.ny, pr.nz = int(dim), int(axis), int(nx), int(ny), int(nz)
+    device = any(_is_torch(a) for a in g if a is not None)
+    pr.mem = RN_MEM_DEVICE if device else RN_MEM_HOST
+    for k in range(3):
+        a = g[k] if k < len(g) else None
+        if a is None:
+            pr.g[k] = None
+            continue
+        if device:
+            if not (a.is_cuda and str(a.dtype) == "torch.float64" and a.is_contiguous()):
+                raise ValueError("device conductances must be contiguous float64 CUDA tensors")
+            pr.g[k] = a.data_ptr()
+        else:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            pr.g[k] = a.ctypes.data
+        keep.append(a)
+    for name, arr, dt in (("p_out", p_out, np.float64), ("mask_out", mask_out, np.uint8)):
+        if arr is None:
+            setattr(pr, name, None)
+            continue
+        if device:
+            setattr(pr, name, arr.data_ptr())
+        else:
+            if not (isinstance(arr, np.ndarray) and arr.dtype == dt and arr.flags["C_CONTIGUOUS"]):
+                raise ValueError(f"{name} must be a C-contiguous {dt.__name__} numpy array")
+            setattr(pr, name, arr.ctypes.data)
+        keep.append(arr)
+    return Problem(pr, keep)
+
+
+class Context:
+    """An rn_ctx on one device (rn_create / rn_destroy)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        h = C.c_void_p()
+        st = lib().rn_create(int(device), C.c_size_t(hbm_budget_bytes), C.byref(h))
+        if st:
+            raise RNError(st)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_error(self) -> str:
+        return lib().rn_last_error(self.h).decode()
+
+    def set_stream(self, stream_handle: Optional[int]):
+        st = lib().rn_set_stream(self.h, C.c_void_p(stream_handle or 0))
+        if st:
+            raise RNError(st)
+
+    def footprint(self, prob: Problem, o: Optional[rn_opts] = None) -> int:
+        return int(lib().rn_footprint(C.byref(prob.c), C.byref(o) if o is not None else None))
+
+    def build_mask(self, prob: Problem) -> int:
+        nl = C.c_int64(0)
+        st = lib().rn_build_mask(self.h, C.byref(prob.c), C.byref(nl))
+        if st:
+            raise RNError(st, self.last_error())
+        return int(nl.value)
+
+    def solve(self, prob: Problem, o: Optional[rn_opts] = None, check: bool = True) -> rn_result:
+        res = rn_result()
+        st = lib().rn_solve(self.h, C.byref(prob.c), C.byref(o) if o is not None else None, C.byref(res))
+        if check and st not in (RN_OK, RN_ENOCONV):
+            raise RNError(st, self.last_error())
+        return res
+
+
+# module-level names matching the C ABI
+def rn_validate(prob: Problem, o: Optional[rn_opts] = None) -> int:
+    return int(lib().rn_validate(C.byref(prob.c), C.byref(o) if o is not None else None))
+
+
+def rn_footprint(prob: Problem, o: Optional[rn_opts] = None) -> int:
+    return int(lib().rn_footprint(C.byref(prob.c), C.byref(o) if o is not None else None))
+
+
+def rn_version() -> int:
+    return int(lib().rn_version())
+
+
+def rn_create(device: int = 0, hbm_budget_bytes: int = 0) -> Context:
+    return Context(device, hbm_budget_bytes)
+
+
+def rn_build_mask(ctx: Context, prob: Problem) -> int:
+    return ctx.build_mask(prob)
+
+
+def rn_solve(ctx: Context, prob: Problem, o: Optional[rn_opts] = None) -> rn_result:
+    return ctx.solve(prob, o)
+
+
+def solve_network(ctx: Context, net, precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000,
+                  want_pressure: bool = False, want_mask: bool = False, delta: float = 0.0):
+    """Host-memory convenience: returns (rn_result, pressure or None, mask or None)."""
+    P = np.zeros(net.shape, dtype=np.float64) if want_pressure else None
+    M = np.zeros(net.shape, dtype=np.uint8) if want_mask else None
+    pr = problem(net, p_out=P, mask_out=M)
+    res = ctx.solve(pr, opts(precision, tol, max_iter, delta))
+    return res, P, M

@@ -1,0 +1,109 @@
+// rn_device.hpp -- structures shared by the host runtime and the gfx950 kernels.
+//
+// The CG state of one network lives in HBM for the whole solve; the host only
+// enqueues launches and reads a small status block now and then.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rn {
+
+// Per-network control block (device memory). One pass kernel launch reads
+// mode / alpha / beta / sigma at entry; the last workgroup to finish reduces
+// the partial sums in a fixed order and writes the next mode and scalars.
+enum PassMode : int32_t { MODE_CG = 0, MODE_REFRESH = 1, MODE_DONE = 2 };
+
+struct Scalars {
+    int32_t mode;       // PassMode of the next launch
+    int32_t status;     // 0 ok, -3 not converged, -4 breakdown
+    int32_t converged;
+    int32_t first;      // the next refresh evaluates b (x = 0)
+    int32_t stop;       // finish after the pending refresh (breakdown path)
+    int32_t fp32;       // inner vectors are FP32
+    int32_t check;      // the pending refresh is a convergence check
+    int32_t pad0_;
+    int64_t iters;      // CG passes executed
+    int64_t refreshes;  // refresh passes executed
+    int64_t passes;     // passes that did work
+    int64_t max_iter;
+    double alpha;       // step of the pending update x += alpha p, r -= alpha q
+    double beta;        // p = r + beta p in the next CG pass
+    double rho;         // exact r_k.z_k of the stored residual at the last CG pass
+    double sigma;       // stored r, p, q are the residual / direction / A p divided by sigma
+    double sigma_next;  // sigma the pending refresh will use
+    double rmax;        // largest stored sqrt(r.z) since the last refresh
+    double tol, delta;
+    double bnorm;       // ||b||_2 (unscaled)
+    double bhat;        // sqrt(b.D^{-1}b)
+    double kappa;       // (||r|| / ||b||) / sqrt(r.D^-1 r / b.D^-1 b), measured at the last refresh
+    double est_rel;     // predicted unscaled relative residual after the last CG pass
+    double rel_resid;   // true relative residual measured by the last refresh
+    double last_check;  // true relative residual at the previous failed convergence check
+    double est_check;   // predicted relative residual that triggered the pending check
+    double Q_in, Q_out, xr;  // fluxes and x.(b - A x) from the last refresh
+    uint32_t ticket;    // workgroups finished in the current launch
+    uint32_t pad_;
+};
+
+// What the host polls (copied to pinned memory after each chunk of launches).
+struct Status {
+    int32_t mode, status;
+    int64_t iters, refreshes, passes;
+    double est_rel, rel_resid;
+};
+
+constexpr int kRed = 5;          // partial sums per workgroup
+constexpr int kBlock = 256;      // threads per workgroup of every kernel here
+constexpr int kWave = 64;
+
+template <typename T>
+struct VecSet {
+    T *r, *p, *q;
+};
+
+// Arguments of the pass kernel (2D and 3D share the layout). Every working
+// pass reads `src` and writes `dst`; the host alternates the two sets.
+template <typename T>
+struct PassArgs {
+    // lattice
+    int nx, ny, nz, axis;
+    int ntx, nty, ntz;           // tile counts
+    int tile_y, tile_z;          // rows per 2D strip / planes per 3D tile
+    int ntiles;                  // total tiles (2D: wave strips; 3D: workgroup tiles)
+    int grid;                    // workgroups launched (multiple of 8)
+    // FP64 data
+    const double *g64[3];        // original conductances
+    double *P[2];                // full FP64 pressure field: CG passes after refresh m add their
+                                 // step to P[m%2] in place; refresh m reads P[m%2], writes P[(m+1)%2]
+    // inner-precision CG state
+    const T *gT[3];              // conductances in the inner precision (0 past the lattice edge)
+    const T *invd;               // Jacobi preconditioner 1/d_i on live nodes, 0 elsewhere
+    VecSet<T> src, dst;
+    // reduction
+    double *partials;            // [grid][kRed]
+    Scalars *s;
+};
+
+struct Lat {
+    int dim, axis, nx, ny, nz;
+    int64_t n;
+};
+
+// launchers (rn_kernels.hip)
+hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long long *bad, hipStream_t st);
+hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
+                       double *dlive, double *P, unsigned long long *n_live, hipStream_t st);
+template <typename T>
+hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dlive, T *const gT[3], T *invd,
+                        T *vec, int64_t nvec, hipStream_t st);
+hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
+template <typename T>
+hipError_t launch_pass(int dim, const PassArgs<T> &a, hipStream_t st);
+
+// 3D tile geometry of the pass kernel
+constexpr int kTX = 64, kTY = 16;
+
+__host__ __device__ inline int div_up(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace rn

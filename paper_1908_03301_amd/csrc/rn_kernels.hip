@@ -1,0 +1,793 @@
+// rn_kernels.hip -- gfx950 kernels of the random-network flow solve.
+//
+// Operator (Sec. II, Eq. 3): on the live set, (A x)_i = sum_j g_ij (x_i - x_j)
+// with x = 0 on the faces for the correction (the face pressures 1 / 0 of the
+// full field enter through b). The CG is Jacobi-preconditioned (M = diag d,
+// d_i = sum_j g_ij) and always applies A in this difference form: rounding the
+// conductances to FP32 then perturbs each bond by a relative 2^-24, which
+// keeps the FP32 operator spectrally within (1 +- 2^-24) of the FP64 one
+// (Rayleigh quotient sum g (x_i - x_j)^2), whatever the condition number.
+//
+// One pass per CG iteration k (single global reduction):
+//     r_k = r_{k-1} - a q_{k-1};  P += sigma a p_{k-1} (FP64);  z_k = r_k / d
+//     p_k = z_k + b p_{k-1};      q_k = A p_k     (5/7-point stencil, p_k recomputed at the halo)
+//     sums p.q, z.q, q.D^-1 q, r.z, r.r in FP64
+// and a = (r.z)/(p.q), r_{k+1}.z_{k+1} = r.z - 2a z.q + a^2 q.D^-1 q give the
+// next step without a second reduction. The solution is accumulated straight
+// into the FP64 pressure field every pass: an FP32 accumulator would round the
+// correction by 2^-24 of its size, i.e. a residual error of order 2^-24 times
+// the condition number at every refresh. Nodes outside the live set read only
+// 1/d (0 there) and write nothing. r, p, q are double-buffered because
+// neighbours read them from the previous pass.
+//
+// The same kernel, in refresh mode, evaluates the FP64 true residual b - A x
+// of the pressure field with the original conductances, the face fluxes and
+// x.(b - A x) for the energy conductance, and restarts the inner recurrence
+// from that residual (reliable update).
+#include "rn_device.hpp"
+
+#include <math.h>
+
+namespace rn {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double ld_coherent(const double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroup index -> tile index so that each XCD (workgroups are dealt to the
+// 8 XCDs round-robin) owns one contiguous range of tiles and shares halos in
+// its own L2. `grid` is a multiple of 8.
+__device__ __forceinline__ int xcd_remap(int b, int grid)
+{
+    const int per = grid >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+// Scalar update after a CG pass. t = (p.q, z.q, q.D^-1 q, r.z, r.r).
+__device__ void step_after_cg(Scalars *s, const double *t)
+{
+    const double pq = t[0], zq = t[1], qq = t[2], rz = t[3];
+    s->passes += 1;
+    s->iters += 1;
+    s->rho = rz;
+    s->rmax = fmax(s->rmax, sqrt(fmax(rz, 0.0)));
+    if (!(rz > 0.0) && isfinite(rz)) {        // residual exactly zero: verify and stop
+        s->alpha = 0.0;
+        s->sigma_next = s->sigma;
+        s->check = 1;
+        s->mode = MODE_REFRESH;
+        return;
+    }
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(zq) || !isfinite(qq) || !isfinite(rz)) {
+        s->status = -4;                       // breakdown: finish on the last good iterate
+        s->stop = 1;
+        s->alpha = 0.0;
+        s->sigma_next = s->sigma;
+        s->mode = MODE_REFRESH;
+        return;
+    }
+    const double alpha = rz / pq;
+    double rho_next = rz - 2.0 * alpha * zq + alpha * alpha * qq;
+    if (!(rho_next > 0.0)) rho_next = 0.0;
+    const double est = s->kappa * s->sigma * sqrt(rho_next) / s->bhat;
+    s->est_rel = est;
+    s->alpha = alpha;
+    const bool check = est <= s->tol || rho_next <= 0.0;
+    const bool refresh = check || s->iters >= s->max_iter ||
+                         (s->delta > 0.0 && sqrt(rho_next) <= s->delta * s->rmax);
+    if (refresh) {
+        s->check = check;
+        s->est_check = est;
+        s->sigma_next = s->sigma * sqrt(fmax(rho_next, rz * 1e-24));
+        s->mode = MODE_REFRESH;
+    } else {
+        s->beta = rho_next / rz;
+        s->mode = MODE_CG;
+    }
+}
+
+// Scalar update after a refresh pass. t = (||r64||^2, r.D^-1 r of the stored residual, x.r64, Q_in, Q_out).
+__device__ void step_after_refresh(Scalars *s, const double *t)
+{
+    const double rr64 = t[0], rrs = t[1];
+    s->passes += 1;
+    s->refreshes += 1;
+    const double sigma_old = s->sigma;
+    const double sigma = s->sigma_next;
+    s->sigma = sigma;
+    const bool first = s->first != 0;
+    if (first) {
+        s->bnorm = sqrt(rr64);
+        s->bhat = sigma * sqrt(rrs);
+        s->kappa = 1.0;
+        s->first = 0;
+    }
+    const double rel = s->bnorm > 0.0 ? sqrt(rr64) / s->bnorm : 0.0;
+    const double srel = s->bhat > 0.0 ? sigma * sqrt(rrs) / s->bhat : 0.0;
+    if (srel > 0.0 && rel > 0.0) s->kappa = rel / srel;
+    s->rel_resid = rel;
+    s->est_rel = rel;
+    s->xr = t[2];
+    s->Q_in = t[3];
+    s->Q_out = t[4];
+    if (s->stop) {
+        s->mode = MODE_DONE;
+    } else if (rel <= s->tol || s->bnorm == 0.0) {
+        s->converged = 1;
+        s->mode = MODE_DONE;
+    } else if (s->iters >= s->max_iter) {
+        s->status = -3;
+        s->mode = MODE_DONE;
+    } else if (!isfinite(rr64) || !isfinite(rrs)) {
+        s->status = -4;
+        s->mode = MODE_DONE;
+    } else if (s->check && !(rel < 0.5 * s->last_check) && rel > 10.0 * s->est_check) {
+        // the recurrence says converged, the true residual is far above it and
+        // no longer halves between checks: its rounding floor is reached
+        s->status = -3;
+        s->mode = MODE_DONE;
+    } else {
+        if (s->check) s->last_check = rel;
+        s->mode = MODE_CG;
+        s->alpha = 0.0;
+        s->beta = first ? 0.0 : sigma * rrs / (sigma_old * s->rho);
+        s->rmax = sqrt(rrs);
+    }
+    s->check = 0;
+}
+
+// Per-workgroup partials, then the last workgroup to arrive reduces them in
+// block order (deterministic) and runs the scalar update.
+__device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, int grid, int mode)
+{
+    __shared__ double red[kBlock / kWave][kRed];
+    __shared__ int is_last;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kRed; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < kRed; ++k) {
+            double v = 0.0;
+            for (int ww = 0; ww < kBlock / kWave; ++ww) v += red[ww][k];
+            partials[(size_t)blockIdx.x * kRed + k] = v;
+        }
+        __threadfence();
+        const unsigned prev = atomicAdd(&s->ticket, 1u);
+        is_last = (prev == (unsigned)grid - 1u);
+    }
+    __syncthreads();
+    if (!is_last) return;
+    __threadfence();
+    double tot[kRed];
+#pragma unroll
+    for (int k = 0; k < kRed; ++k) tot[k] = 0.0;
+    for (int b = threadIdx.x; b < grid; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < kRed; ++k) tot[k] += ld_coherent(&partials[(size_t)b * kRed + k]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRed; ++k) {
+        double v = wave_sum(tot[k]);
+        if (lane == 0) red[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t[kRed];
+        for (int k = 0; k < kRed; ++k) {
+            t[k] = 0.0;
+            for (int ww = 0; ww < kBlock / kWave; ++ww) t[k] += red[ww][k];
+        }
+        if (mode == MODE_CG) step_after_cg(s, t);
+        else step_after_refresh(s, t);
+        s->ticket = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- refresh (FP64)
+// Node-local FP64 work of a refresh pass. The pending step sa p (sa = sigma a)
+// is added on the fly to every pressure the stencil reads; p is zero off the
+// live set, so Ps + sa p is the updated field everywhere.
+template <typename T, int DIM>
+__device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
+                                             double *__restrict__ Pd, int x, int y, int z, double sa,
+                                             double sigma_next, double (&acc)[kRed])
+{
+    const int64_t sx = 1, sy = a.nx, sz = (int64_t)a.nx * a.ny;
+    const int64_t i = x + sy * y + sz * z;
+    const double di = (double)a.invd[i];
+    if (di == 0.0) {
+        Pd[i] = Ps[i];
+        return;
+    }
+    auto pn = [&](int64_t j) -> double { return Ps[j] + sa * (double)a.src.p[j]; };
+    const double pi = pn(i);
+    double r64 = 0.0, qin = 0.0, qout = 0.0;
+    const int c[3] = {x, y, z};
+    const int n[3] = {a.nx, a.ny, a.nz};
+    const int64_t st[3] = {sx, sy, sz};
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        if (c[k] > 0) {
+            const double g = a.g64[k][i - st[k]];
+            if (g != 0.0) {
+                r64 += g * (pn(i - st[k]) - pi);
+                if (k == a.axis && c[k] == 1) qin += g * (1.0 - pi);
+            }
+        }
+        if (c[k] + 1 < n[k]) {
+            const double g = a.g64[k][i];
+            if (g != 0.0) {
+                r64 += g * (pn(i + st[k]) - pi);
+                if (k == a.axis && c[k] == n[k] - 2) qout += g * pi;
+            }
+        }
+    }
+    const T rs = (T)(r64 / sigma_next);
+    Pd[i] = pi;
+    a.dst.r[i] = rs;
+    a.dst.p[i] = a.src.p[i];
+    a.dst.q[i] = T(0);
+    acc[0] += r64 * r64;
+    acc[1] += (double)rs * (double)rs * di;
+    acc[2] += pi * r64;
+    acc[3] += qin;
+    acc[4] += qout;
+}
+
+// ---------------------------------------------------------------- 2D pass
+// A wave owns a strip of 64 consecutive x and `tile_y` rows; it streams down
+// y keeping p' of rows y-1, y, y+1 in registers. x-neighbours come from
+// lane shuffles; lanes 0 and 63 also evaluate p' one column outside the strip.
+template <typename T>
+__device__ __forceinline__ void cg2d_strip(const PassArgs<T> &a, double *__restrict__ P, int x, int y0, int y1,
+                                           int lane, T alpha, T beta, double sa, double (&acc)[kRed])
+{
+    const int nx = a.nx, ny = a.ny;
+    const bool valid = x < nx;
+    const int xh = (lane == 0) ? x - 1 : x + 1;          // halo column of lanes 0 / 63
+    const bool hv = (lane == 0 || lane == kWave - 1) && xh >= 0 && xh < nx;
+    const T *__restrict__ rs = a.src.r;
+    const T *__restrict__ qs = a.src.q;
+    const T *__restrict__ ps = a.src.p;
+    const T *__restrict__ dv = a.invd;
+    T *__restrict__ rd = a.dst.r;
+    T *__restrict__ qd = a.dst.q;
+    T *__restrict__ pd = a.dst.p;
+    const T *__restrict__ gx = a.gT[0];
+    const T *__restrict__ gy = a.gT[1];
+
+    auto pnew = [&](int yy, int xx, bool ok) -> T {
+        if (!ok || yy < 0 || yy >= ny) return T(0);
+        const int64_t i = (int64_t)yy * nx + xx;
+        const T d = dv[i];
+        if (d == T(0)) return T(0);
+        return d * (rs[i] - alpha * qs[i]) + beta * ps[i];
+    };
+    // interior row: r', z', p'; r' and the FP64 pressure are stored right away
+    auto load_row = [&](int yy, T &pv, T &rv, T &zv, T &dvi, T &ph) {
+        pv = rv = zv = dvi = T(0);
+        if (valid) {
+            const int64_t i = (int64_t)yy * nx + x;
+            dvi = dv[i];
+            if (dvi != T(0)) {
+                const T pold = ps[i];
+                rv = rs[i] - alpha * qs[i];
+                zv = dvi * rv;
+                pv = zv + beta * pold;
+                P[i] += sa * (double)pold;
+                rd[i] = rv;
+            }
+        }
+        ph = pnew(yy, xh, hv);
+    };
+
+    T pm = pnew(y0 - 1, x, valid);
+    T pc, rc, zc, dc, phc;
+    load_row(y0, pc, rc, zc, dc, phc);
+    for (int yy = y0; yy < y1; ++yy) {
+        T pn, rn, zn, dn, phn;
+        if (yy + 1 < y1) {
+            load_row(yy + 1, pn, rn, zn, dn, phn);
+        } else {
+            pn = pnew(yy + 1, x, valid);
+            phn = pnew(yy + 1, xh, hv);
+            rn = zn = dn = T(0);
+        }
+        const int64_t i = (int64_t)yy * nx + x;
+        const bool live = dc != T(0);
+        const T gxc = live ? gx[i] : T(0);
+        const T gyc = live ? gy[i] : T(0);
+        T pl = __shfl_up(pc, 1, kWave);
+        T pr = __shfl_down(pc, 1, kWave);
+        const T gxl = (live && x >= 1) ? gx[i - 1] : T(0);
+        const T gym = (live && yy >= 1) ? gy[i - nx] : T(0);
+        if (lane == 0) pl = phc;
+        if (lane == kWave - 1) pr = phc;
+        T qv = T(0);
+        if (live) {
+            qv = gxl * (pc - pl) + gxc * (pc - pr) + gym * (pc - pm) + gyc * (pc - pn);
+            pd[i] = pc;
+            qd[i] = qv;
+        }
+        const double dp = (double)pc, dq = (double)qv, dz = (double)zc, dr = (double)rc;
+        acc[0] += dp * dq;
+        acc[1] += dz * dq;
+        acc[2] += dq * dq * (double)dc;
+        acc[3] += dr * dz;
+        acc[4] += dr * dr;
+        pm = pc;
+        pc = pn;
+        rc = rn;
+        zc = zn;
+        dc = dn;
+        phc = phn;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pass2d_kernel(PassArgs<T> a)
+{
+    Scalars *s = a.s;
+    const int mode = s->mode;
+    if (mode == MODE_DONE) return;
+    double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int tile = xcd_remap(blockIdx.x, a.grid) * (kBlock / kWave) + w;
+    const int m = (int)(s->refreshes & 1);
+    const double sa = s->sigma * s->alpha;
+    if (tile < a.ntiles) {
+        const int tx = tile % a.ntx, ty = tile / a.ntx;
+        const int x = tx * kWave + lane;
+        const int y0 = ty * a.tile_y;
+        const int y1 = min(y0 + a.tile_y, a.ny);
+        if (mode == MODE_CG) {
+            cg2d_strip<T>(a, a.P[m], x, y0, y1, lane, (T)s->alpha, (T)s->beta, sa, acc);
+        } else if (x < a.nx) {
+            const double sigma_next = s->sigma_next;
+            for (int yy = y0; yy < y1; ++yy)
+                refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
+        }
+    }
+    finish_pass(acc, a.partials, s, a.grid, mode);
+}
+
+// ---------------------------------------------------------------- 3D pass
+// A workgroup owns a 64 (x) x 16 (y) x tile_z (z) block; each wave covers 4
+// rows. It streams up z: the p' plane (with a one-node halo ring) is staged in
+// a triple-buffered LDS tile, p' of planes z-1, z, z+1 stays in registers.
+constexpr int kRows = kTY / (kBlock / kWave);
+
+template <typename T>
+__device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int y0, int z0,
+                                          int z1, T alpha, T beta, double sa, double (&acc)[kRed])
+{
+    __shared__ T lp[3][kTY + 2][kTX + 2];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int x = x0 + lane;
+    const T *__restrict__ rs = a.src.r;
+    const T *__restrict__ qs = a.src.q;
+    const T *__restrict__ ps = a.src.p;
+    const T *__restrict__ dv = a.invd;
+    T *__restrict__ rd = a.dst.r;
+    T *__restrict__ qd = a.dst.q;
+    T *__restrict__ pd = a.dst.p;
+    const T *__restrict__ gx = a.gT[0];
+    const T *__restrict__ gy = a.gT[1];
+    const T *__restrict__ gz = a.gT[2];
+
+    auto pnew = [&](int xx, int yy, int zz) -> T {
+        if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return T(0);
+        const int64_t i = xx + sy * yy + sz * zz;
+        const T d = dv[i];
+        if (d == T(0)) return T(0);
+        return d * (rs[i] - alpha * qs[i]) + beta * ps[i];
+    };
+
+    T pz[3][kRows];          // p' of planes zz-2, zz-1, zz (ring indexed by plane % 3)
+    T rz[2][kRows];          // r' of planes zz-1, zz (ring by plane % 2)
+    T dz[2][kRows];          // 1/d of planes zz-1, zz
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+        pz[0][j] = pz[1][j] = pz[2][j] = T(0);
+        rz[0][j] = rz[1][j] = T(0);
+        dz[0][j] = dz[1][j] = T(0);
+    }
+
+    for (int zz = z0 - 1; zz <= z1; ++zz) {
+        const int b = (zz + 3) % 3;          // zz >= -1
+        const int h = (zz + 2) & 1;
+        const bool inner = zz >= z0 && zz < z1;
+        // ---- stage plane zz: own rows
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            const int yy = y0 + w * kRows + j;
+            T pv = T(0), rv = T(0), dvi = T(0);
+            if (x < nx && yy < ny && zz >= 0 && zz < nz) {
+                const int64_t i = x + sy * yy + sz * zz;
+                dvi = dv[i];
+                if (dvi != T(0)) {
+                    const T pold = ps[i];
+                    rv = rs[i] - alpha * qs[i];
+                    pv = dvi * rv + beta * pold;
+                    if (inner) {
+                        P[i] += sa * (double)pold;
+                        rd[i] = rv;
+                    }
+                }
+            }
+            pz[b][j] = pv;
+            rz[h][j] = rv;
+            dz[h][j] = dvi;
+            lp[b][1 + w * kRows + j][1 + lane] = pv;
+        }
+        // ---- halo ring of plane zz
+        if (w == 0) {
+            lp[b][0][1 + lane] = pnew(x, y0 - 1, zz);
+        } else if (w == 1) {
+            lp[b][kTY + 1][1 + lane] = pnew(x, y0 + kTY, zz);
+        } else if (w == 2) {
+            if (lane < kTY) lp[b][1 + lane][0] = pnew(x0 - 1, y0 + lane, zz);
+            else if (lane < 2 * kTY) lp[b][1 + lane - kTY][kTX + 1] = pnew(x0 + kTX, y0 + lane - kTY, zz);
+        }
+        __syncthreads();
+        // ---- stencil on plane zc = zz - 1
+        const int zc = zz - 1;
+        if (zc >= z0 && zc < z1) {
+            const int bc = (zc + 3) % 3, bm = (zc + 2) % 3, hc = (zc + 2) & 1;
+#pragma unroll
+            for (int j = 0; j < kRows; ++j) {
+                const int ly = 1 + w * kRows + j;
+                const int yy = y0 + w * kRows + j;
+                const T pc = pz[bc][j];
+                const T dc = dz[hc][j];
+                T qv = T(0);
+                if (dc != T(0)) {                     // live node (inside the lattice)
+                    const int64_t i = x + sy * yy + sz * zc;
+                    const T gxc = gx[i];
+                    const T gxl = x >= 1 ? gx[i - 1] : T(0);
+                    const T gyc = gy[i];
+                    const T gyl = yy >= 1 ? gy[i - sy] : T(0);
+                    const T gzc = gz[i];
+                    const T gzl = zc >= 1 ? gz[i - sz] : T(0);
+                    qv = gxl * (pc - lp[bc][ly][lane]) + gxc * (pc - lp[bc][ly][lane + 2]) +
+                         gyl * (pc - lp[bc][ly - 1][1 + lane]) + gyc * (pc - lp[bc][ly + 1][1 + lane]) +
+                         gzl * (pc - pz[bm][j]) + gzc * (pc - pz[b][j]);
+                    pd[i] = pc;
+                    qd[i] = qv;
+                }
+                const double dp = (double)pc, dq = (double)qv, dr = (double)rz[hc][j];
+                const double dd = (double)dc, dzv = dd * dr;
+                acc[0] += dp * dq;
+                acc[1] += dzv * dq;
+                acc[2] += dq * dq * dd;
+                acc[3] += dr * dzv;
+                acc[4] += dr * dr;
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void pass3d_kernel(PassArgs<T> a)
+{
+    Scalars *s = a.s;
+    const int mode = s->mode;
+    if (mode == MODE_DONE) return;
+    double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int tile = xcd_remap(blockIdx.x, a.grid);
+    const int m = (int)(s->refreshes & 1);
+    const double sa = s->sigma * s->alpha;
+    // tile index is uniform per workgroup: idle workgroups still reach the reduction
+    if (tile < a.ntiles) {
+        const int tx = tile % a.ntx;
+        const int ty = (tile / a.ntx) % a.nty;
+        const int tz = tile / (a.ntx * a.nty);
+        const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
+        const int z1 = min(z0 + a.tile_z, a.nz);
+        if (mode == MODE_CG) {
+            cg3d_tile<T>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, sa, acc);
+        } else {
+            const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+            const double sigma_next = s->sigma_next;
+            const int x = x0 + lane;
+            if (x < a.nx)
+                for (int j = 0; j < kRows; ++j) {
+                    const int yy = y0 + w * kRows + j;
+                    if (yy >= a.ny) break;
+                    for (int zz = z0; zz < z1; ++zz)
+                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, sa, sigma_next, acc);
+                }
+        }
+    }
+    finish_pass(acc, a.partials, s, a.grid, mode);
+}
+
+// ---------------------------------------------------------------- setup kernels
+
+__device__ __forceinline__ void coords(const Lat &L, int64_t i, int &x, int &y, int &z)
+{
+    x = (int)(i % L.nx);
+    const int64_t t = i / L.nx;
+    y = (int)(t % L.ny);
+    z = (int)(t / L.ny);
+}
+
+__device__ __forceinline__ int face_code(const Lat &L, int x, int y, int z)
+{
+    const int c = L.axis == 0 ? x : (L.axis == 1 ? y : z);
+    const int na = L.axis == 0 ? L.nx : (L.axis == 1 ? L.ny : L.nz);
+    return c == 0 ? 1 : (c == na - 1 ? 2 : 0);
+}
+
+// Count in-lattice conductances that are negative, NaN or infinite.
+__global__ void validate_kernel(Lat L, const double *g0, const double *g1, const double *g2,
+                                unsigned long long *bad)
+{
+    unsigned long long cnt = 0;
+    const double *g[3] = {g0, g1, g2};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        const int c[3] = {x, y, z};
+        const int n[3] = {L.nx, L.ny, L.nz};
+        for (int k = 0; k < L.dim; ++k) {
+            if (c[k] + 1 >= n[k]) continue;
+            const double v = g[k][i];
+            if (!(v >= 0.0) || isinf(v)) ++cnt;
+        }
+    }
+    if (cnt) atomicAdd(bad, cnt);
+}
+
+// Lock-free union-find on int32 labels: a root is linked under the smaller
+// root by CAS, so every component ends with its minimum node index as root,
+// whatever the order of the unions.
+__device__ __forceinline__ int uf_load(const int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int uf_find(int *parent, int x)
+{
+    while (true) {
+        const int p = uf_load(parent + x);
+        if (p == x) return x;
+        const int gp = uf_load(parent + p);
+        if (gp != p) __hip_atomic_store(parent + x, gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x = gp;
+    }
+}
+
+__device__ __forceinline__ void uf_union(int *parent, int a, int b)
+{
+    while (true) {
+        a = uf_find(parent, a);
+        b = uf_find(parent, b);
+        if (a == b) return;
+        if (a < b) {
+            const int t = a;
+            a = b;
+            b = t;
+        }
+        int expected = a;
+        if (__hip_atomic_compare_exchange_strong(parent + a, &expected, b, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return;
+    }
+}
+
+__global__ void uf_init_kernel(int64_t n, int *parent, unsigned *flags)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        parent[i] = (int)i;
+        flags[i] = 0u;
+    }
+}
+
+// Union across every occupied bond joining two interior nodes.
+__global__ void uf_union_kernel(Lat L, const double *g0, const double *g1, const double *g2, int *parent)
+{
+    const double *g[3] = {g0, g1, g2};
+    const int64_t st[3] = {1, L.nx, (int64_t)L.nx * L.ny};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        if (face_code(L, x, y, z)) continue;
+        const int c[3] = {x, y, z};
+        const int n[3] = {L.nx, L.ny, L.nz};
+        for (int k = 0; k < L.dim; ++k) {
+            if (c[k] + 1 >= n[k] || !(g[k][i] > 0.0)) continue;
+            if (k == L.axis && c[k] + 1 == n[k] - 1) continue;     // neighbour on the outlet face
+            uf_union(parent, (int)i, (int)(i + st[k]));
+        }
+    }
+}
+
+// Tag each component with the faces it touches through occupied bonds (only
+// neighbours along the flow axis can be face nodes).
+__global__ void uf_flags_kernel(Lat L, const double *ga, int *parent, unsigned *flags)
+{
+    const int64_t sa = L.axis == 0 ? 1 : (L.axis == 1 ? (int64_t)L.nx : (int64_t)L.nx * L.ny);
+    const int na = L.axis == 0 ? L.nx : (L.axis == 1 ? L.ny : L.nz);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        const int c = L.axis == 0 ? x : (L.axis == 1 ? y : z);
+        if (c == 0 || c == na - 1) continue;
+        unsigned bits = 0u;
+        if (c == 1 && ga[i - sa] > 0.0) bits |= 1u;
+        if (c == na - 2 && ga[i] > 0.0) bits |= 2u;
+        if (bits) atomicOr(flags + uf_find(parent, (int)i), bits);
+    }
+}
+
+// Mask byte, diagonal d_i (live nodes, 0 elsewhere), initial pressure field
+// (faces 1 / 0, dead nodes 1 when tied to the inlet only, live nodes 0) and
+// the live count.
+__global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, const double *g2,
+                                  int *parent, const unsigned *flags, uint8_t *mask, double *dlive,
+                                  double *P, unsigned long long *n_live)
+{
+    const double *g[3] = {g0, g1, g2};
+    const int64_t st[3] = {1, L.nx, (int64_t)L.nx * L.ny};
+    unsigned long long cnt = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        const int f = face_code(L, x, y, z);
+        uint8_t m;
+        double s = 0.0, p0;
+        if (f == 1) {
+            m = 5;
+            p0 = 1.0;
+        } else if (f == 2) {
+            m = 6;
+            p0 = 0.0;
+        } else {
+            m = (uint8_t)flags[uf_find(parent, (int)i)];
+            p0 = (m == 1) ? 1.0 : 0.0;
+            if (m == 3) {
+                const int c[3] = {x, y, z};
+                const int n[3] = {L.nx, L.ny, L.nz};
+                double d = 0.0;
+                for (int k = 0; k < L.dim; ++k) {
+                    if (c[k] > 0) d += g[k][i - st[k]];
+                    if (c[k] + 1 < n[k]) d += g[k][i];
+                }
+                s = d;
+                ++cnt;
+            }
+        }
+        if (mask) mask[i] = m;
+        dlive[i] = s;
+        P[i] = p0;
+    }
+    cnt = (unsigned long long)wave_sum((double)cnt);
+    if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(n_live, cnt);
+}
+
+// Conductances and Jacobi preconditioner in the inner precision, and zeroed CG state.
+template <typename T>
+__global__ void scale_kernel(Lat L, const double *g0, const double *g1, const double *g2,
+                             const double *dlive, T *h0, T *h1, T *h2, T *invd, T *vec, int64_t nvec)
+{
+    const double *g[3] = {g0, g1, g2};
+    T *h[3] = {h0, h1, h2};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        const int c[3] = {x, y, z};
+        const int n[3] = {L.nx, L.ny, L.nz};
+        for (int k = 0; k < L.dim; ++k) h[k][i] = (c[k] + 1 < n[k]) ? (T)g[k][i] : T(0);
+        const double d = dlive[i];
+        invd[i] = d > 0.0 ? (T)(1.0 / d) : T(0);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
+         i += (int64_t)gridDim.x * blockDim.x)
+        vec[i] = T(0);
+}
+
+// Sum of direct inlet-outlet bonds (only when the flow axis has 2 planes).
+__global__ void direct_flux_kernel(Lat L, const double *ga, double *out)
+{
+    __shared__ double red[kBlock / kWave];
+    const int64_t sa = L.axis == 0 ? 1 : (L.axis == 1 ? (int64_t)L.nx : (int64_t)L.nx * L.ny);
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < L.n; i += blockDim.x) {
+        int x, y, z;
+        coords(L, i, x, y, z);
+        if (face_code(L, x, y, z) != 1) continue;
+        const double v = ga[i];
+        if (v > 0.0) acc += v;
+        (void)sa;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < kBlock / kWave; ++k) t += red[k];
+        *out = t;
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+
+static inline int grid_for(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long long *bad, hipStream_t st)
+{
+    validate_kernel<<<grid_for(L.n), kBlock, 0, st>>>(L, g[0], g[1], L.dim == 3 ? g[2] : nullptr, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
+                       double *dlive, double *P, unsigned long long *n_live, hipStream_t st)
+{
+    const int gr = grid_for(L.n);
+    const double *g2 = L.dim == 3 ? g[2] : nullptr;
+    uf_init_kernel<<<gr, kBlock, 0, st>>>(L.n, parent, flags);
+    uf_union_kernel<<<gr, kBlock, 0, st>>>(L, g[0], g[1], g2, parent);
+    uf_flags_kernel<<<gr, kBlock, 0, st>>>(L, g[L.axis], parent, flags);
+    mask_final_kernel<<<gr, kBlock, 0, st>>>(L, g[0], g[1], g2, parent, flags, mask, dlive, P, n_live);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dlive, T *const gT[3], T *invd,
+                        T *vec, int64_t nvec, hipStream_t st)
+{
+    scale_kernel<T><<<grid_for(L.n), kBlock, 0, st>>>(L, g[0], g[1], L.dim == 3 ? g[2] : nullptr, dlive, gT[0],
+                                                      gT[1], L.dim == 3 ? gT[2] : nullptr, invd, vec, nvec);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st)
+{
+    direct_flux_kernel<<<1, kBlock, 0, st>>>(L, ga, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pass(int dim, const PassArgs<T> &a, hipStream_t st)
+{
+    if (dim == 2) pass2d_kernel<T><<<a.grid, kBlock, 0, st>>>(a);
+    else pass3d_kernel<T><<<a.grid, kBlock, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_scale<float>(const Lat &, const double *const[3], const double *, float *const[3],
+                                        float *, float *, int64_t, hipStream_t);
+template hipError_t launch_scale<double>(const Lat &, const double *const[3], const double *, double *const[3],
+                                         double *, double *, int64_t, hipStream_t);
+template hipError_t launch_pass<float>(int, const PassArgs<float> &, hipStream_t);
+template hipError_t launch_pass<double>(int, const PassArgs<double> &, hipStream_t);
+
+}  // namespace rn

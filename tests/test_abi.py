@@ -1,0 +1,120 @@
+"""The C-ABI library on the CPU: it loads, exports what include/rn.h declares,
+and validates arguments before any device call (no GPU needed here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1908_03301_amd import binding as B
+from paper_1908_03301_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1908_03301_amd import build
+        build.build()
+    return B.lib()
+
+
+def declared_symbols():
+    hdr = open(os.path.join(ROOT, "include", "rn.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(rn_[a-z_]+)\s*\(", hdr)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_symbols()
+    assert "rn_solve" in names and "rn_build_mask" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_strerror_and_defaults(lib):
+    assert B.strerror(0) == "ok"
+    assert B.strerror(-3) == "not converged"
+    assert B.strerror(-99) == "unknown status"
+    o = B.opts()
+    assert o.precision == B.RN_FP64 and o.tol == 1e-8 and o.max_iter == 10_000_000
+    assert B.rn_version() >= 100
+
+
+def test_struct_layout_matches_header(lib):
+    # sizes of the three ABI structs, compiled from rn.h by the host compiler
+    src = '#include "rn.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu",sizeof(rn_problem),' \
+          'sizeof(rn_opts),sizeof(rn_result));return 0;}\n'
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        open(os.path.join(d, "t.c"), "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), os.path.join(d, "t.c"), "-o",
+                               os.path.join(d, "t")])
+        out = subprocess.check_output([os.path.join(d, "t")]).decode().split()
+    assert [int(v) for v in out] == [C.sizeof(B.rn_problem), C.sizeof(B.rn_opts), C.sizeof(B.rn_result)]
+
+
+def _prob(**kw):
+    net = I.uniform_network(2, 8, 6)
+    p = B.problem(net)
+    for k, v in kw.items():
+        setattr(p.c, k, v)
+    return p
+
+
+def test_validate_rejects_bad_arguments(lib):
+    assert B.rn_validate(_prob()) == B.RN_OK
+    assert B.rn_validate(_prob(dim=4)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(nz=2)) == B.RN_EINVAL          # 2D needs nz == 1
+    assert B.rn_validate(_prob(axis=2)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(nx=0)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(mem=7)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(reserved=1)) == B.RN_EINVAL
+    p = _prob()
+    p.c.g[1] = None
+    assert B.rn_validate(p) == B.RN_EINVAL
+    # flow axis with a single plane
+    net = I.uniform_network(2, 1, 6)
+    assert B.rn_validate(B.problem(net)) == B.RN_EINVAL
+    # option checks
+    assert B.rn_validate(_prob(), B.opts(tol=0.0)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(), B.opts(precision=5)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(), B.opts(max_iter=-1)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(), B.opts(delta=1.5)) == B.RN_EINVAL
+
+
+@pytest.mark.parametrize("bad", [-1.0, np.nan, np.inf])
+def test_validate_rejects_bad_conductance(lib, bad):
+    net = I.uniform_network(3, 5, 4, 3)
+    g = [a.copy() for a in net.g]
+    g[2][1, 2, 3] = bad
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 0))) == B.RN_EINVAL
+    # the same value past the lattice edge is ignored
+    g = [a.copy() for a in net.g]
+    g[2][-1, 2, 3] = bad
+    g[0][1, 1, -1] = bad
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 0))) == B.RN_OK
+
+
+def test_footprint(lib):
+    net = I.uniform_network(2, 2048, 2048)
+    n = 2048 * 2048
+    f64 = B.rn_footprint(B.problem(net), B.opts(B.RN_FP64))
+    f32 = B.rn_footprint(B.problem(net), B.opts(B.RN_MIXED))
+    # host input: FP64 copy of g (16) + P x2 (16) + diagonal (8) + mask (1), then in the
+    # inner precision s: dim conductance arrays, 1/d and two sets of r, p, q
+    assert f64 >= n * (16 + 16 + 8 + 1 + 8 * (2 + 1 + 6))
+    assert f32 >= n * (16 + 16 + 8 + 1 + 4 * (2 + 1 + 6))
+    assert f32 < f64 < n * 120
+    assert B.rn_footprint(_prob(dim=5)) == 0
+
+
+def test_null_context_is_rejected(lib):
+    res = B.rn_result()
+    assert lib.rn_solve(None, C.byref(_prob().c), None, C.byref(res)) == B.RN_EINVAL
+    assert lib.rn_build_mask(None, C.byref(_prob().c), None) == B.RN_EINVAL
+    assert lib.rn_destroy(None) == B.RN_OK

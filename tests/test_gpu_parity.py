@@ -1,0 +1,294 @@
+"""GPU parity: librn (HIP, gfx950) against the CPU oracle, through the C ABI.
+
+Bars: the connectivity mask is bit-exact; K in FP64 within 1e-9 relative of
+an oracle solved to 1e-13, within 1e-7 for the mixed-precision path; the
+pressure field within a bound derived from the residual tolerance; the true
+residual of the returned field, evaluated by the oracle, within tol.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_03301_amd import binding as B
+from paper_1908_03301_amd import inputs as I
+from tests import _pins
+
+pytestmark = pytest.mark.gpu
+
+K_TOL = {B.RN_FP64: 1e-9, B.RN_MIXED: 1e-7}
+SOLVE_TOL = {B.RN_FP64: 1e-10, B.RN_MIXED: 1e-8}
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    say("rn_create device 0")
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_solve(ctx, net, precision, tol=None, max_iter=500_000):
+    tol = SOLVE_TOL[precision] if tol is None else tol
+    say(f"solve dim={net.dim} shape={net.shape} axis={net.axis} prec={precision} tol={tol} {net.meta}")
+    res, P, M = B.solve_network(ctx, net, precision, tol, max_iter, want_pressure=True, want_mask=True)
+    return res, P, M
+
+
+def check_against_oracle(oracle_mod, net, res, P, M, precision, ref=None):
+    if ref is None:
+        ref = oracle_mod.solve(net, tol=1e-13, want_mask=True)
+    np.testing.assert_array_equal(M, ref.mask)
+    assert res.n_live == ref.n_live
+    assert res.converged == 1 and res.status == 0, res.as_dict()
+    assert res.rel_resid <= SOLVE_TOL[precision]
+    # the oracle re-evaluates the returned field with its own operator
+    c = oracle_mod.check_pressure(net, P)
+    assert c.rel_resid <= SOLVE_TOL[precision] * 1.01
+    assert res.K == pytest.approx(ref.K, rel=K_TOL[precision], abs=1e-300)
+    # G from the device reduction vs the oracle's energy form of the returned
+    # field: the oracle's residual d_i x_i - sum g_ij x_j cancels to ~1e-13
+    # absolute at these conductance contrasts, so the bar is the K bar.
+    assert res.G == pytest.approx(c.G_E, rel=1e-9, abs=1e-300)
+    assert res.Q_in == pytest.approx(c.Q_in, rel=1e-11, abs=1e-14)
+    assert res.Q_out == pytest.approx(c.Q_out, rel=1e-11, abs=1e-14)
+    # pressures: faces and dead nodes exact, live nodes close to the oracle's
+    live = ref.mask == 3
+    np.testing.assert_array_equal(P[~live], ref.pressure[~live])
+    if ref.n_live:
+        err = np.max(np.abs(P[live] - ref.pressure[live]))
+        assert err <= 1e-4 if precision == B.RN_MIXED else err <= 1e-6
+    return ref
+
+
+# ------------------------------------------------------------------ golden and closed forms
+
+@pytest.mark.parametrize("name", ["hand_3x2.json", "hand_3x1x2.json"])
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_golden(ctx, name, precision):
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+    g = [np.array(d["g_x"]), np.array(d["g_y"])] + ([np.array(d["g_z"])] if d["dim"] == 3 else [])
+    net = I.Network(d["dim"], d["nx"], d["ny"], d["nz"], g, d["axis"])
+    res, P, M = gpu_solve(ctx, net, precision, tol=1e-12)
+    np.testing.assert_array_equal(M, np.array(d["mask"], dtype=np.uint8))
+    np.testing.assert_allclose(P, np.array(d["pressure"]), atol=1e-11)
+    assert res.K == pytest.approx(d["K"], rel=1e-11)
+
+
+@pytest.mark.parametrize("dim,shape", [(2, (130, 70, 1)), (2, (64, 33, 1)), (2, (2, 50, 1)), (2, (300, 5, 1)),
+                                       (3, (67, 35, 20)), (3, (16, 16, 3)), (3, (5, 70, 18))])
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_uniform_closed_form(ctx, dim, shape, precision):
+    nx, ny, nz = shape
+    for axis in range(dim):
+        net = I.uniform_network(dim, nx, ny, nz, g0=2.5, axis=axis)
+        if _pins.axis_len(net) < 2:
+            continue
+        res, P, M = gpu_solve(ctx, net, precision)
+        assert res.K == pytest.approx(2.5, rel=K_TOL[precision])
+        # Q_out - Q_in is the sum of the residual entries: |sum r| <= sqrt(n_live) ||r||,
+        # with ||r|| <= tol ||b|| and ||b|| = g0 sqrt(S) (one inlet bond per node of plane 1)
+        bnorm = 2.5 * np.sqrt(_pins.cross_section(net))
+        assert abs(res.Q_out - res.Q_in) <= np.sqrt(res.n_live) * SOLVE_TOL[precision] * bnorm
+
+
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_stratified_3d_closed_form(ctx, precision):
+    net = I.stratified_network(40, H=0.8, sigma=2.0, occupancy=1.0, index=5, nx=70, ny=36, nz=40)
+    phi = net.meta["phi"]
+    A = np.exp(2.0 * phi).mean()
+    Hm = 1.0 / np.mean(1.0 / np.exp(2.0 * 0.5 * (phi[:-1] + phi[1:])))
+    for axis, want in ((0, A), (1, A), (2, Hm)):
+        res, P, M = gpu_solve(ctx, net.with_axis(axis), precision)
+        assert res.K == pytest.approx(want, rel=K_TOL[precision])
+
+
+# ------------------------------------------------------------------ parity with the oracle
+
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_iid_128(ctx, oracle_mod, precision):
+    """128^2, ln g ~ N(0,1) i.i.d., flow along x (the small workload)."""
+    net = I.workload_iid_2d_128()
+    res, P, M = gpu_solve(ctx, net, precision)
+    check_against_oracle(oracle_mod, net, res, P, M, precision)
+
+
+@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_fbm_diluted_2d(ctx, oracle_mod, case, precision):
+    nx, ny, occ, H = [(200, 150, 0.6, 0.7), (129, 257, 0.55, 0.35), (64, 64, 0.8, 0.9), (333, 47, 0.65, 0.7)][case]
+    base = I.fbm_network(2, nx, ny, 1, H=H, sigma=1.5, occupancy=occ, index=500 + case)
+    for axis in range(2):
+        net = base.with_axis(axis)
+        res, P, M = gpu_solve(ctx, net, precision)
+        check_against_oracle(oracle_mod, net, res, P, M, precision)
+
+
+@pytest.mark.parametrize("case", range(3))
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_fbm_diluted_3d(ctx, oracle_mod, case, precision):
+    nx, ny, nz, occ = [(70, 40, 37, 0.35), (33, 33, 33, 0.3), (65, 17, 50, 0.6)][case]
+    base = I.fbm_network(3, nx, ny, nz, H=0.7, sigma=1.0, occupancy=occ, index=600 + case)
+    for axis in range(3):
+        net = base.with_axis(axis)
+        res, P, M = gpu_solve(ctx, net, precision)
+        check_against_oracle(oracle_mod, net, res, P, M, precision)
+
+
+def test_stratified_near_threshold_3d(ctx, oracle_mod):
+    net = I.stratified_network(48, H=0.8, sigma=2.0, occupancy=0.3, index=7)
+    for axis in (0, 2):
+        res, P, M = gpu_solve(ctx, net.with_axis(axis), B.RN_MIXED)
+        check_against_oracle(oracle_mod, net.with_axis(axis), res, P, M, B.RN_MIXED)
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_edge_cases(ctx, oracle_mod):
+    # non-percolating (2D far below p_c = 1/2): nothing live, K = 0
+    net = I.iid_network(2, 80, 80, 1, occupancy=0.25, index=9)
+    res, P, M = gpu_solve(ctx, net, B.RN_FP64)
+    ref = oracle_mod.solve(net, tol=1e-12, want_mask=True)
+    assert res.n_live == 0 == ref.n_live and res.K == 0.0 and res.iters == 0 and res.converged
+    np.testing.assert_array_equal(M, ref.mask)
+    np.testing.assert_array_equal(P, ref.pressure)
+    # two planes along the axis: direct bonds only
+    rng = np.random.default_rng(2)
+    gx = rng.uniform(0.1, 2, (37, 2))
+    gx[5, 0] = 0.0
+    net = I.Network(2, 2, 37, 1, [gx, rng.uniform(0.1, 2, (37, 2))], 0)
+    res, P, M = gpu_solve(ctx, net, B.RN_FP64)
+    assert res.G == pytest.approx(gx[:, 0].sum(), rel=1e-14)
+    # series chain, one node wide, in 2D and 3D
+    g = np.array([[0.5, 2.0, 3.0, 0.25, 4.0, 1.0, 0.0]])
+    res, P, M = gpu_solve(ctx, I.Network(2, 7, 1, 1, [g, np.zeros_like(g)], 0), B.RN_FP64)
+    assert res.G == pytest.approx(1.0 / np.sum(1.0 / g[0, :6]), rel=1e-10)
+    g3 = np.zeros((9, 1, 1))
+    g3[:8, 0, 0] = np.linspace(0.5, 4, 8)
+    res, P, M = gpu_solve(ctx, I.Network(3, 1, 1, 9, [np.zeros_like(g3), np.zeros_like(g3), g3], 2), B.RN_MIXED)
+    assert res.G == pytest.approx(1.0 / np.sum(1.0 / g3[:8, 0, 0]), rel=1e-7)
+    # three planes: every interior node touches both faces
+    net = I.fbm_network(3, 3, 40, 30, H=0.7, sigma=1.5, occupancy=0.7, index=10)
+    res, P, M = gpu_solve(ctx, net, B.RN_FP64)
+    check_against_oracle(oracle_mod, net, res, P, M, B.RN_FP64)
+
+
+def test_not_converged_and_invalid(ctx):
+    net = I.fbm_network(2, 200, 200, 1, H=0.7, sigma=1.5, occupancy=0.7, index=11)
+    res, P, M = gpu_solve(ctx, net, B.RN_FP64, max_iter=5)
+    assert res.status == B.RN_ENOCONV and res.converged == 0 and res.iters == 5
+    bad = [a.copy() for a in net.g]
+    bad[1][3, 4] = -1.0
+    with pytest.raises(B.RNError) as e:
+        ctx.solve(B.problem(I.Network(2, 200, 200, 1, bad, 0)), B.opts())
+    assert e.value.code == B.RN_EINVAL
+
+
+def test_device_memory_and_determinism(ctx, oracle_mod):
+    import torch
+    net = I.fbm_network(3, 48, 40, 36, H=0.7, sigma=1.5, occupancy=0.45, index=12)
+    say("device-memory solve")
+    gd = [torch.from_numpy(a).cuda() for a in net.g]
+    Pd = torch.zeros(net.shape, dtype=torch.float64, device="cuda")
+    Md = torch.zeros(net.shape, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    pr = B.problem(dim=3, nx=net.nx, ny=net.ny, nz=net.nz, axis=0, g=gd, p_out=Pd, mask_out=Md)
+    r1 = ctx.solve(pr, B.opts(B.RN_FP64, 1e-10))
+    P1 = Pd.cpu().numpy().copy()
+    check_against_oracle(oracle_mod, net, r1, P1, Md.cpu().numpy(), B.RN_FP64)
+    r2 = ctx.solve(pr, B.opts(B.RN_FP64, 1e-10))
+    assert r2.K == r1.K and r2.iters == r1.iters           # bit-identical: fixed reduction order
+    np.testing.assert_array_equal(Pd.cpu().numpy(), P1)
+    # host-memory path gives the same bits
+    r3, P3, _ = B.solve_network(ctx, net, B.RN_FP64, 1e-10, want_pressure=True)
+    assert r3.K == r1.K
+    np.testing.assert_array_equal(P3, P1)
+    # invalid device data is caught on the device
+    gd[0][2, 3, 4] = float("nan")
+    with pytest.raises(B.RNError) as e:
+        ctx.solve(pr, B.opts())
+    assert e.value.code == B.RN_EINVAL
+
+
+def test_build_mask_entry_point(ctx, oracle_mod):
+    for dim, shape, occ in ((2, (300, 200, 1), 0.52), (3, (60, 50, 40), 0.26)):
+        net = I.iid_network(dim, *shape, occupancy=occ, index=13)
+        for axis in range(dim):
+            n2 = net.with_axis(axis)
+            M = np.zeros(n2.shape, dtype=np.uint8)
+            say(f"rn_build_mask dim={dim} shape={shape} axis={axis}")
+            nl = ctx.build_mask(B.problem(n2, mask_out=M))
+            ref, nref = oracle_mod.mask_bfs(n2)
+            np.testing.assert_array_equal(M, ref)
+            assert nl == nref
+
+
+# ------------------------------------------------------------------ full-size workloads
+
+def test_full_2048_fbm(ctx, oracle_mod):
+    """2048^2 FBM (H=0.7, sigma=1.5, occupancy 0.6), K_x and K_y, FP64 to 1e-10.
+
+    The oracle checks the mask bit for bit and re-evaluates the residual,
+    fluxes and energy of the returned field with its own operator.
+    """
+    net = I.workload_fbm_2d_2048()
+    for axis in (0, 1):
+        n2 = net.with_axis(axis)
+        res, P, M = gpu_solve(ctx, n2, B.RN_FP64)
+        ref_mask, nl = oracle_mod.mask_bfs(n2)
+        np.testing.assert_array_equal(M, ref_mask)
+        assert res.converged and res.rel_resid <= 1e-10
+        c = oracle_mod.check_pressure(n2, P)
+        assert c.rel_resid <= 1.01e-10
+        assert res.G == pytest.approx(c.G_E, rel=1e-9)
+        assert c.Q_out == pytest.approx(c.Q_in, rel=1e-6)
+        assert c.p_min >= -1e-12 and c.p_max <= 1 + 1e-12
+        say(f"K axis {axis} = {res.K!r} iters {res.iters} loop {res.t_loop_s:.3f}s")
+
+
+def test_full_2048_duality(ctx):
+    """Planar duality at 2048^2 (undiluted FBM): G(primal) G(dual, 1/g) = 1."""
+    net = I.fbm_network(2, 2048, 2048, 1, H=0.7, sigma=1.5, occupancy=1.0, index=0)
+    dual = _pins.dual_2d_fast(net)
+    r1, _, _ = gpu_solve(ctx, net, B.RN_FP64, tol=1e-11)
+    r2, _, _ = gpu_solve(ctx, dual, B.RN_FP64, tol=1e-11)
+    assert r1.G * r2.G == pytest.approx(1.0, rel=1e-9)
+
+
+@pytest.mark.timeout(900)
+def test_full_256_stratified(ctx, oracle_mod):
+    """256^3 layered medium (1D FBM along z, H=0.8, sigma=2), mixed precision to 1e-8.
+
+    Occupancy 1.0: K_x and K_z equal the arithmetic / harmonic layer means
+    exactly. Occupancy 0.27 (near the 3D bond threshold): the mask is checked
+    bit for bit against the oracle, the oracle re-evaluates the residual, and
+    K_x, K_z stay below the undiluted closed forms (Rayleigh monotonicity).
+    """
+    full = I.workload_strat_3d_256(occupancy=1.0)
+    phi = full.meta["phi"]
+    A = np.exp(2.0 * phi).mean()
+    Hm = 1.0 / np.mean(1.0 / np.exp(2.0 * 0.5 * (phi[:-1] + phi[1:])))
+    for axis, want in ((0, A), (2, Hm)):
+        res, P, M = gpu_solve(ctx, full.with_axis(axis), B.RN_MIXED)
+        assert res.K == pytest.approx(want, rel=1e-7)
+    del full
+    net = I.workload_strat_3d_256()
+    for axis, bound in ((0, A), (2, Hm)):
+        n2 = net.with_axis(axis)
+        res, P, M = gpu_solve(ctx, n2, B.RN_MIXED)
+        say(f"K axis {axis} = {res.K!r} live {res.n_live} iters {res.iters} refreshes {res.refreshes}")
+        ref_mask, nl = oracle_mod.mask_bfs(n2)
+        np.testing.assert_array_equal(M, ref_mask)
+        c = oracle_mod.check_pressure(n2, P)
+        assert res.converged and c.rel_resid <= 1.01e-8
+        assert res.G == pytest.approx(c.G_E, rel=1e-9)
+        assert 0.0 < res.K <= bound

@@ -152,6 +152,13 @@ def test_planar_duality(oracle_mod, shape, H):
     assert g1 * g2 == pytest.approx(1.0, rel=1e-11)
 
 
+def test_dual_constructions_agree():
+    net = I.fbm_network(2, 9, 7, 1, H=0.7, sigma=1.0, index=1)
+    a, b = _pins.dual_2d(net), _pins.dual_2d_fast(net)
+    for k in range(2):
+        np.testing.assert_array_equal(a.g[k], b.g[k])
+
+
 def test_iid_2d_self_dual_mean(oracle_mod):
     """ln g symmetric about 0 in 2D: K is close to exp<ln g> = 1 (statistical, loose band)."""
     net = I.iid_network(2, 48, 48, 1, sigma=1.0, index=5)
