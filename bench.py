@@ -114,6 +114,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle PCG iterations in the CPU sample")
+    ap.add_argument("--single-axis", action="store_true", help="solve only the first flow axis (profiling)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -127,7 +130,21 @@ def main():
     from paper_1908_03301_amd import binding as B
     from paper_1908_03301_amd import inputs as I
 
-    wl = WORKLOADS[args.workload]
+    if args.calibrate_copy:
+        # reference dispatch for the HBM byte counters: reads and writes exactly
+        # MIB MiB each (a copy between two fresh buffers, repeated 3 times)
+        nbytes = args.calibrate_copy << 20
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes}), flush=True)
+        return
+
+    wl = dict(WORKLOADS[args.workload])
+    if args.single_axis:
+        wl["axes"] = wl["axes"][:1]
     net = wl["make"](I)
     torch.cuda.set_device(0)
     gd = [torch.from_numpy(a).to("cuda") for a in net.g]

@@ -122,7 +122,7 @@ Layout make_layout(const rn_problem *p, const rn_opts *o, int tile_y, int tile_z
     L.tile_z = tile_z;
     if (p->dim == 2) {
         L.ntx = div_up((int)p->nx, kWave);
-        L.nty = div_up((int)p->ny, tile_y);
+        L.nty = div_up((int)p->ny, L.s == 4 ? kTY2f : kTY2d);
         L.ntz = 1;
         L.ntiles = L.ntx * L.nty;
         L.grid = div_up(L.ntiles, kBlock / kWave);
@@ -307,13 +307,15 @@ int run_loop(rn_ctx *ctx, const rn_problem *p, const rn_opts *o, const Layout &L
             RN_TRY(hipEventSynchronize(ctx->ev_chunk[pending]));
             const Scalars &h = ctx->host_scal[pending];
             if (h.mode == MODE_DONE) break;
-            // size the next chunk from the observed convergence rate
-            int next = std::min(chunk * 2, 1024);
+            // size the next chunk from the observed convergence rate; the
+            // chunk enqueued last is still in flight, and launches left over
+            // after convergence are idle, so aim slightly short
+            int next = std::min(chunk * 2, 256);
             if (prev_est > 0.0 && h.est_rel > 0.0 && h.est_rel < prev_est && h.iters > prev_iters) {
                 const double rate = std::log(prev_est / h.est_rel) / (double)(h.iters - prev_iters);
                 const double remain = std::log(std::max(h.est_rel / o->tol, 1.0)) / rate;
-                const double want = 1.1 * remain - (double)last_chunk + 2.0;
-                next = (int)std::min(1024.0, std::max(4.0, want));
+                const double want = 0.9 * remain - (double)last_chunk;
+                next = (int)std::min(256.0, std::max(8.0, want));
             }
             prev_est = h.est_rel;
             prev_iters = h.iters;

@@ -101,8 +101,9 @@ hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipSt
 template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> &a, hipStream_t st);
 
-// 3D tile geometry of the pass kernel
-constexpr int kTX = 64, kTY = 16;
+// tile geometry of the pass kernels: 2D tiles are 64 x kTY2f (FP32) or
+// 64 x kTY2d (FP64) per wave, 3D tiles 64 x kTY x tile_z per workgroup
+constexpr int kTX = 64, kTY = 16, kTY2f = 8, kTY2d = 4;
 
 __host__ __device__ inline int div_up(int a, int b) { return (a + b - 1) / b; }
 

@@ -39,9 +39,17 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-__device__ __forceinline__ double ld_coherent(const double *p)
+// Partial sums travel between workgroups through write-through (system-scope)
+// stores and loads that bypass the per-XCD L2s, so no workgroup has to write
+// back or invalidate its L2 (a device-scope fence would do both).
+__device__ __forceinline__ double ld_through(const double *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+__device__ __forceinline__ void st_through(double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Workgroup index -> tile index so that each XCD (workgroups are dealt to the
@@ -163,21 +171,23 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, i
         for (int k = 0; k < kRed; ++k) {
             double v = 0.0;
             for (int ww = 0; ww < kBlock / kWave; ++ww) v += red[ww][k];
-            partials[(size_t)blockIdx.x * kRed + k] = v;
+            st_through(&partials[(size_t)blockIdx.x * kRed + k], v);
         }
-        __threadfence();
-        const unsigned prev = atomicAdd(&s->ticket, 1u);
+        // wait until this thread's write-through stores have completed
+        // (s_waitcnt with every counter at 0), then take a ticket
+        // (device-scope atomic, coherent across XCDs)
+        __builtin_amdgcn_s_waitcnt(0);
+        const unsigned prev = __hip_atomic_fetch_add(&s->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         is_last = (prev == (unsigned)grid - 1u);
     }
     __syncthreads();
     if (!is_last) return;
-    __threadfence();
     double tot[kRed];
 #pragma unroll
     for (int k = 0; k < kRed; ++k) tot[k] = 0.0;
     for (int b = threadIdx.x; b < grid; b += kBlock)
 #pragma unroll
-        for (int k = 0; k < kRed; ++k) tot[k] += ld_coherent(&partials[(size_t)b * kRed + k]);
+        for (int k = 0; k < kRed; ++k) tot[k] += ld_through(&partials[(size_t)b * kRed + k]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRed; ++k) {
@@ -249,17 +259,28 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 }
 
 // ---------------------------------------------------------------- 2D pass
-// A wave owns a strip of 64 consecutive x and `tile_y` rows; it streams down
-// y keeping p' of rows y-1, y, y+1 in registers. x-neighbours come from
-// lane shuffles; lanes 0 and 63 also evaluate p' one column outside the strip.
+// A wave owns a tile of 64 consecutive x and TY rows. Every load of the tile
+// (its TY rows, one halo row above and below, the halo columns, the bonds and
+// the FP64 pressures) is issued up front at a clamped, in-bounds address with
+// no branch on loaded data, so the tile's whole memory traffic is in flight
+// at once; out-of-lattice values are then zeroed with selects. Off the live
+// set r = q = p = 0 in memory, so the arithmetic needs no mask; only stores are
+// restricted to live nodes. x-neighbours come from lane shuffles; lanes 0..TY-1
+// and 64-TY..63 load the halo columns x0-1 and x0+64 (one row each), which
+// shuffles hand to lanes 0 and 63.
 template <typename T>
-__device__ __forceinline__ void cg2d_strip(const PassArgs<T> &a, double *__restrict__ P, int x, int y0, int y1,
-                                           int lane, T alpha, T beta, double sa, double (&acc)[kRed])
+struct Tile2D {
+    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;
+};
+
+template <typename T>
+__device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x, int y0, int lane,
+                                          T alpha, T beta, double sa, double (&acc)[kRed])
 {
+    constexpr int TY = Tile2D<T>::TY;
     const int nx = a.nx, ny = a.ny;
     const bool valid = x < nx;
-    const int xh = (lane == 0) ? x - 1 : x + 1;          // halo column of lanes 0 / 63
-    const bool hv = (lane == 0 || lane == kWave - 1) && xh >= 0 && xh < nx;
+    const int xc = valid ? x : nx - 1;
     const T *__restrict__ rs = a.src.r;
     const T *__restrict__ qs = a.src.q;
     const T *__restrict__ ps = a.src.p;
@@ -269,72 +290,92 @@ __device__ __forceinline__ void cg2d_strip(const PassArgs<T> &a, double *__restr
     T *__restrict__ pd = a.dst.p;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
+    auto rowc = [&](int yy) { return yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy); };
 
-    auto pnew = [&](int yy, int xx, bool ok) -> T {
-        if (!ok || yy < 0 || yy >= ny) return T(0);
-        const int64_t i = (int64_t)yy * nx + xx;
-        const T d = dv[i];
-        if (d == T(0)) return T(0);
-        return d * (rs[i] - alpha * qs[i]) + beta * ps[i];
-    };
-    // interior row: r', z', p'; r' and the FP64 pressure are stored right away
-    auto load_row = [&](int yy, T &pv, T &rv, T &zv, T &dvi, T &ph) {
-        pv = rv = zv = dvi = T(0);
-        if (valid) {
-            const int64_t i = (int64_t)yy * nx + x;
-            dvi = dv[i];
-            if (dvi != T(0)) {
-                const T pold = ps[i];
-                rv = rs[i] - alpha * qs[i];
-                zv = dvi * rv;
-                pv = zv + beta * pold;
-                P[i] += sa * (double)pold;
-                rd[i] = rv;
-            }
-        }
-        ph = pnew(yy, xh, hv);
-    };
+    // ---- issue every load
+    T d_[TY + 2], r_[TY + 2], q_[TY + 2], p_[TY + 2];
+#pragma unroll
+    for (int j = 0; j < TY + 2; ++j) {
+        const int64_t i = (int64_t)rowc(y0 - 1 + j) * nx + xc;
+        d_[j] = dv[i];
+        r_[j] = rs[i];
+        q_[j] = qs[i];
+        p_[j] = ps[i];
+    }
+    double Pv[TY];
+    T gxv[TY], gyv[TY + 1];
+#pragma unroll
+    for (int j = 0; j < TY; ++j) {
+        const int64_t i = (int64_t)rowc(y0 + j) * nx + xc;
+        Pv[j] = P[i];
+        gxv[j] = gx[i];
+        gyv[j + 1] = gy[i];
+    }
+    gyv[0] = y0 >= 1 ? gy[(int64_t)(y0 - 1) * nx + xc] : T(0);   // bond below the tile (none at y = 0)
+    // halo columns: lane l < TY holds (x0-1, y0+l), lane 64-TY+l holds (x0+64, y0+l)
+    const bool hleft = lane < TY, hright = lane >= kWave - TY;
+    const int hrow = hleft ? lane : lane - (kWave - TY);
+    const int x0 = x - lane;
+    const int hx = hleft ? x0 - 1 : x0 + kWave;
+    const bool hok = (hleft || hright) && hx >= 0 && hx < nx && y0 + hrow < ny;
+    T hd = T(0), hr = T(0), hq = T(0), hp = T(0), hg = T(0);
+    if (hok) {
+        const int64_t i = (int64_t)(y0 + hrow) * nx + hx;
+        hd = dv[i];
+        hr = rs[i];
+        hq = qs[i];
+        hp = ps[i];
+        hg = hleft ? gx[i] : T(0);        // bond (x0-1) -> x0 for lane 0
+    }
 
-    T pm = pnew(y0 - 1, x, valid);
-    T pc, rc, zc, dc, phc;
-    load_row(y0, pc, rc, zc, dc, phc);
-    for (int yy = y0; yy < y1; ++yy) {
-        T pn, rn, zn, dn, phn;
-        if (yy + 1 < y1) {
-            load_row(yy + 1, pn, rn, zn, dn, phn);
-        } else {
-            pn = pnew(yy + 1, x, valid);
-            phn = pnew(yy + 1, xh, hv);
-            rn = zn = dn = T(0);
-        }
-        const int64_t i = (int64_t)yy * nx + x;
-        const bool live = dc != T(0);
-        const T gxc = live ? gx[i] : T(0);
-        const T gyc = live ? gy[i] : T(0);
+    // ---- p' on all TY + 2 rows, r' and the pressure step on the TY interior rows
+    T pv[TY + 2];
+#pragma unroll
+    for (int j = 0; j < TY + 2; ++j) {
+        const int yy = y0 - 1 + j;
+        const bool ok = valid && yy >= 0 && yy < ny;
+        const T v = d_[j] * (r_[j] - alpha * q_[j]) + beta * p_[j];
+        pv[j] = ok ? v : T(0);
+    }
+    const T hpv = hd * (hr - alpha * hq) + beta * hp;   // zero when !hok (all inputs zero)
+#pragma unroll
+    for (int j = 0; j < TY; ++j) {
+        const int yy = y0 + j;
+        const bool ok = valid && yy < ny;
+        const T dc = ok ? d_[j + 1] : T(0);
+        const T rc = ok ? r_[j + 1] - alpha * q_[j + 1] : T(0);
+        const T pc = pv[j + 1];
+        // neighbours across x
         T pl = __shfl_up(pc, 1, kWave);
         T pr = __shfl_down(pc, 1, kWave);
-        const T gxl = (live && x >= 1) ? gx[i - 1] : T(0);
-        const T gym = (live && yy >= 1) ? gy[i - nx] : T(0);
-        if (lane == 0) pl = phc;
-        if (lane == kWave - 1) pr = phc;
-        T qv = T(0);
-        if (live) {
-            qv = gxl * (pc - pl) + gxc * (pc - pr) + gym * (pc - pm) + gyc * (pc - pn);
+        T gxl = __shfl_up(gxv[j], 1, kWave);
+        const T hl = __shfl(hpv, j, kWave);
+        const T hrr = __shfl(hpv, kWave - TY + j, kWave);
+        const T hgl = __shfl(hg, j, kWave);
+        if (lane == 0) {
+            pl = hl;
+            gxl = hgl;
+        }
+        if (lane == kWave - 1) pr = hrr;
+        T qv = gxl * (pc - pl) + gxv[j] * (pc - pr) + gyv[j] * (pc - pv[j]) + gyv[j + 1] * (pc - pv[j + 2]);
+        if (dc == T(0)) qv = T(0);
+        // every in-lattice node is stored (zeros and unchanged pressures off the
+        // live set) so that cache lines are written whole
+        if (ok) {
+            const int64_t i = (int64_t)yy * nx + x;
+            P[i] = Pv[j] + sa * (double)p_[j + 1];
+            rd[i] = rc;
             pd[i] = pc;
             qd[i] = qv;
         }
-        const double dp = (double)pc, dq = (double)qv, dz = (double)zc, dr = (double)rc;
+        const double dq = (double)qv;
+        const double dp = (double)pc, dr = (double)rc;
+        const double dd = (double)dc, dz = dd * dr;
         acc[0] += dp * dq;
         acc[1] += dz * dq;
-        acc[2] += dq * dq * (double)dc;
+        acc[2] += dq * dq * dd;
         acc[3] += dr * dz;
         acc[4] += dr * dr;
-        pm = pc;
-        pc = pn;
-        rc = rn;
-        zc = zn;
-        dc = dn;
-        phc = phn;
     }
 }
 
@@ -352,10 +393,10 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(PassArgs<T> a)
     if (tile < a.ntiles) {
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         const int x = tx * kWave + lane;
-        const int y0 = ty * a.tile_y;
-        const int y1 = min(y0 + a.tile_y, a.ny);
+        const int y0 = ty * Tile2D<T>::TY;
+        const int y1 = min(y0 + Tile2D<T>::TY, a.ny);
         if (mode == MODE_CG) {
-            cg2d_strip<T>(a, a.P[m], x, y0, y1, lane, (T)s->alpha, (T)s->beta, sa, acc);
+            cg2d_tile<T>(a, a.P[m], x, y0, lane, (T)s->alpha, (T)s->beta, sa, acc);
         } else if (x < a.nx) {
             const double sigma_next = s->sigma_next;
             for (int yy = y0; yy < y1; ++yy)
@@ -395,7 +436,6 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return T(0);
         const int64_t i = xx + sy * yy + sz * zz;
         const T d = dv[i];
-        if (d == T(0)) return T(0);
         return d * (rs[i] - alpha * qs[i]) + beta * ps[i];
     };
 
@@ -421,14 +461,12 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             if (x < nx && yy < ny && zz >= 0 && zz < nz) {
                 const int64_t i = x + sy * yy + sz * zz;
                 dvi = dv[i];
-                if (dvi != T(0)) {
-                    const T pold = ps[i];
-                    rv = rs[i] - alpha * qs[i];
-                    pv = dvi * rv + beta * pold;
-                    if (inner) {
-                        P[i] += sa * (double)pold;
-                        rd[i] = rv;
-                    }
+                const T pold = ps[i];
+                rv = rs[i] - alpha * qs[i];
+                pv = dvi * rv + beta * pold;
+                if (inner) {
+                    P[i] += sa * (double)pold;
+                    rd[i] = rv;
                 }
             }
             pz[b][j] = pv;
@@ -457,7 +495,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
                 const T pc = pz[bc][j];
                 const T dc = dz[hc][j];
                 T qv = T(0);
-                if (dc != T(0)) {                     // live node (inside the lattice)
+                if (x < nx && yy < ny) {
                     const int64_t i = x + sy * yy + sz * zc;
                     const T gxc = gx[i];
                     const T gxl = x >= 1 ? gx[i - 1] : T(0);
@@ -468,6 +506,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
                     qv = gxl * (pc - lp[bc][ly][lane]) + gxc * (pc - lp[bc][ly][lane + 2]) +
                          gyl * (pc - lp[bc][ly - 1][1 + lane]) + gyc * (pc - lp[bc][ly + 1][1 + lane]) +
                          gzl * (pc - pz[bm][j]) + gzc * (pc - pz[b][j]);
+                    if (dc == T(0)) qv = T(0);
                     pd[i] = pc;
                     qd[i] = qv;
                 }
