@@ -32,8 +32,9 @@
  *   - All caller buffers are borrowed for the duration of the call and never
  *     freed by the library. Device memory the library needs belongs to the
  *     rn_ctx and is bounded by its HBM budget.
- *   - Calls on one rn_ctx are serialised by the caller (not thread-safe);
- *     different contexts are independent.
+ *   - Calls on one rn_ctx are serialised internally; rn_submit, rn_poll and
+ *     rn_stats may be called from any thread. Different contexts are
+ *     independent.
  */
 #ifndef RN_H
 #define RN_H
@@ -102,10 +103,13 @@ typedef struct {
     int64_t iters;      /* CG iterations */
     int64_t refreshes;  /* FP64 true-residual refreshes (the first one computes b) */
     int64_t n_live;     /* interior nodes connected to both faces */
-    int64_t passes;     /* kernel launches of the iteration loop (including idle ones) */
+    int64_t passes;     /* pass rounds launched while this network iterated (a round launches
+                           one pass kernel per kind of network present; idle rounds after
+                           convergence, until the host notices, are included) */
     double t_mask_s;    /* device time: upload, validation and connectivity */
-    double t_loop_s;    /* device time: iteration loop (all passes) */
-    double t_total_s;   /* host wall time of the call */
+    double t_loop_s;    /* device time from the start of this network's iterations to the
+                           end of its last round */
+    double t_total_s;   /* host wall time from the call (or rn_submit) to completion */
 } rn_result;
 
 /* Library version, 100 * major + minor. */
@@ -175,6 +179,60 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
  * RN_EINVAL / RN_ENOMEM / RN_EDEVICE before it (outputs untouched).
  */
 int rn_solve(rn_ctx *ctx, const rn_problem *prob, const rn_opts *opts, rn_result *out);
+
+/*
+ * Solve `count` independent networks together (the batched form of rn_solve).
+ * opts holds n_opts entries: 0 (opts may be NULL: defaults for all), 1 (the
+ * same options for all) or count (one per network). out receives count
+ * results. Networks of any size, dimension and precision share each pass
+ * launch while keeping their own reductions and convergence; a network's
+ * result is bit-identical to rn_solve of it alone. Networks wait for device
+ * memory when the HBM budget is exhausted and start as others finish.
+ * Returns RN_OK when every network converged, else the first non-OK
+ * network status (per-network status in out[i].status); RN_EINVAL /
+ * RN_ENOMEM (a network larger than the whole budget) / RN_EDEVICE before
+ * any solve, with outputs untouched.
+ */
+int rn_solve_batch(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opts *opts, int32_t n_opts,
+                   rn_result *out);
+
+/*
+ * Serving: queue one network for solving and return at once with a ticket.
+ * The first call starts the context's server thread, which admits queued
+ * networks as device memory (the HBM budget, per rn_footprint) and control
+ * slots allow, runs every admitted network in the same pass launches
+ * (continuous batching: a network joins at the next chunk boundary and leaves
+ * as soon as it converges) and frees its memory at once. The buffers named
+ * by prob (g, p_out, mask_out) must stay valid and unmodified until rn_poll
+ * returns for that ticket. Errors: RN_EINVAL, RN_ENOMEM (larger than the whole
+ * budget); nothing is queued then. Thread-safe with rn_poll and rn_stats.
+ * After the first rn_submit, rn_set_stream and rn_build_mask return
+ * RN_EINVAL; rn_solve and rn_solve_batch go through the server.
+ */
+int rn_submit(rn_ctx *ctx, const rn_problem *prob, const rn_opts *opts, uint64_t *ticket_out);
+
+/*
+ * Result of a submitted network: RN_EAGAIN while it is queued or running;
+ * once it is done, fills *out, forgets the ticket and returns out->status
+ * (RN_OK, RN_ENOCONV, RN_ENUMERIC, RN_EINVAL for device-resident invalid
+ * values, RN_ENOMEM, RN_EDEVICE); RN_ENOTFOUND for an unknown or already
+ * collected ticket. out->t_total_s is the time from rn_submit to completion.
+ */
+int rn_poll(rn_ctx *ctx, uint64_t ticket, rn_result *out);
+
+/* Scheduler occupancy of a context (for monitoring and admission tests). */
+typedef struct {
+    int64_t waiting;      /* queued, waiting for memory or a control slot */
+    int64_t preparing;    /* setup (upload, mask) in flight */
+    int64_t active;       /* in the pass launches */
+    int64_t finishing;    /* outputs being copied back */
+    int64_t bytes_in_use; /* device bytes held by networks */
+    int64_t budget;       /* the context's HBM budget */
+    int64_t launches;     /* pass kernel launches issued so far */
+    int64_t peak_active;  /* most networks that have shared one pass launch */
+} rn_stats_t;
+
+int rn_stats(rn_ctx *ctx, rn_stats_t *out);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,8 @@ RN_FP64, RN_MIXED = 0, 1
 RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
-            "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve"]
+            "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
+            "rn_submit", "rn_poll", "rn_stats"]
 
 
 class rn_problem(C.Structure):
@@ -43,6 +44,14 @@ class rn_result(C.Structure):
                 ("rel_resid", C.c_double), ("iters", C.c_int64), ("refreshes", C.c_int64),
                 ("n_live", C.c_int64), ("passes", C.c_int64),
                 ("t_mask_s", C.c_double), ("t_loop_s", C.c_double), ("t_total_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rn_stats_t(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("waiting", "preparing", "active", "finishing", "bytes_in_use", "budget",
+                                          "launches", "peak_active")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,7 +89,12 @@ def lib():
         L.rn_footprint.restype = C.c_size_t
         L.rn_build_mask.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
         L.rn_solve.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(rn_result)]
-        for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve"):
+        L.rn_solve_batch.argtypes = [C.c_void_p, C.c_int32, P(rn_problem), P(rn_opts), C.c_int32, P(rn_result)]
+        L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
+        L.rn_poll.argtypes = [C.c_void_p, C.c_uint64, P(rn_result)]
+        L.rn_stats.argtypes = [C.c_void_p, P(rn_stats_t)]
+        for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve",
+                  "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -203,6 +217,44 @@ class Context:
         if check and st not in (RN_OK, RN_ENOCONV):
             raise RNError(st, self.last_error())
         return res
+
+
+    def solve_batch(self, probs: Sequence[Problem], o=None, check: bool = True) -> List[rn_result]:
+        """rn_solve_batch: o is None (defaults), one rn_opts, or a list with one per problem."""
+        n = len(probs)
+        arr = (rn_problem * n)(*[pb.c for pb in probs])
+        res = (rn_result * n)()
+        if o is None:
+            opt_arr, n_opts = None, 0
+        elif isinstance(o, rn_opts):
+            opt_arr, n_opts = (rn_opts * 1)(o), 1
+        else:
+            opt_arr, n_opts = (rn_opts * n)(*o), n
+        st = lib().rn_solve_batch(self.h, n, arr, opt_arr, n_opts, res)
+        if check and st not in (RN_OK, RN_ENOCONV, RN_ENUMERIC):
+            raise RNError(st, self.last_error())
+        return [res[i] for i in range(n)]
+
+    def submit(self, prob: Problem, o: Optional[rn_opts] = None) -> int:
+        """rn_submit: queue a solve; prob's buffers must outlive the ticket."""
+        t = C.c_uint64(0)
+        st = lib().rn_submit(self.h, C.byref(prob.c), C.byref(o) if o is not None else None, C.byref(t))
+        if st:
+            raise RNError(st, self.last_error())
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """rn_poll: (status, rn_result) with status RN_EAGAIN while running."""
+        res = rn_result()
+        st = lib().rn_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        return st, res
+
+    def stats(self) -> dict:
+        s = rn_stats_t()
+        st = lib().rn_stats(self.h, C.byref(s))
+        if st:
+            raise RNError(st)
+        return s.as_dict()
 
 
 # module-level names matching the C ABI

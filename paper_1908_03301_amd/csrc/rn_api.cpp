@@ -1,35 +1,25 @@
-// rn_api.cpp -- C ABI of librn: argument checks, device memory, launch
-// sequencing and result assembly for the random-network flow solve.
+// rn_api.cpp -- C ABI of librn (include/rn.h).
 //
-// The iteration loop is device-driven: every pass kernel reads the next mode
-// (CG step, FP64 refresh, done) written by the previous pass, so the host only
-// enqueues launches in chunks and reads the control block between chunks.
-#include "../../include/rn.h"
-#include "rn_device.hpp"
+// Every solve goes through one scheduler per context: a submitted network
+// waits for device memory (the HBM budget) and a control slot, is prepared
+// (upload, validation, connectivity), joins the engine's pass rounds at the
+// next chunk boundary, and leaves it as soon as it converges, releasing its
+// memory for the next one (continuous batching). rn_solve and rn_solve_batch
+// drive the scheduler on the calling thread; rn_submit starts a server thread
+// that drives it in the background.
+#include "rn_runtime.hpp"
 
-#include <hip/hip_runtime.h>
-
+#include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <cstdio>
 #include <cstring>
-#include <string>
 
 using namespace rn;
 
-struct rn_ctx {
-    int device = 0;
-    size_t budget = 0;
-    hipStream_t own = nullptr;
-    hipStream_t stream = nullptr;
-    std::string err;
-    void *arena = nullptr;
-    size_t arena_bytes = 0;
-    Scalars *host_scal = nullptr;  // pinned [3]
-    unsigned long long *host_cnt = nullptr;  // pinned [2]
-    hipEvent_t ev_chunk[2] = {nullptr, nullptr};
-    hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
-    int tile_y = 16, tile_z = 16;
+struct rn_server {
+    std::thread th;
+    std::condition_variable cv;
+    bool stop = false;
 };
 
 namespace {
@@ -46,306 +36,296 @@ const char *kStatusNames[] = {"ok", "invalid argument", "out of memory", "not co
         }                                                                             \
     } while (0)
 
-inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-// Shape checks shared by every entry point (no data access).
-int check_shape(const rn_problem *p)
-{
-    if (!p) return RN_EINVAL;
-    if (p->dim != 2 && p->dim != 3) return RN_EINVAL;
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return RN_EINVAL;
-    if (p->dim == 2 && p->nz != 1) return RN_EINVAL;
-    if (p->axis < 0 || p->axis >= p->dim) return RN_EINVAL;
-    const int64_t na = p->axis == 0 ? p->nx : (p->axis == 1 ? p->ny : p->nz);
-    if (na < 2) return RN_EINVAL;
-    if (p->nx > INT32_MAX || p->ny > INT32_MAX || p->nz > INT32_MAX) return RN_EINVAL;
-    const double n = (double)p->nx * (double)p->ny * (double)p->nz;
-    if (n >= 2147483647.0) return RN_EINVAL;
-    if (p->mem != RN_MEM_HOST && p->mem != RN_MEM_DEVICE) return RN_EINVAL;
-    if (p->reserved != 0) return RN_EINVAL;
-    for (int k = 0; k < p->dim; ++k)
-        if (!p->g[k]) return RN_EINVAL;
-    if (p->dim == 2 && p->g[2]) return RN_EINVAL;
-    return RN_OK;
-}
-
-int check_opts(const rn_opts *o)
-{
-    if (!o) return RN_EINVAL;
-    if (o->precision != RN_FP64 && o->precision != RN_MIXED) return RN_EINVAL;
-    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RN_EINVAL;
-    if (o->max_iter < 0) return RN_EINVAL;
-    if (!(o->delta >= 0.0) || o->delta >= 1.0) return RN_EINVAL;
-    if (o->reserved != 0) return RN_EINVAL;
-    return RN_OK;
-}
-
-// Host-memory conductances: finite and >= 0 on every in-lattice bond.
-bool host_values_ok(const rn_problem *p)
-{
-    const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
-    for (int k = 0; k < p->dim; ++k) {
-        const double *g = p->g[k];
-        for (int64_t z = 0; z < nz; ++z)
-            for (int64_t y = 0; y < ny; ++y) {
-                const double *row = g + nx * (y + ny * z);
-                int64_t xe = nx;
-                if (k == 0) xe = nx - 1;
-                else if (k == 1 && y == ny - 1) xe = 0;
-                else if (k == 2 && z == nz - 1) xe = 0;
-                for (int64_t x = 0; x < xe; ++x) {
-                    const double v = row[x];
-                    if (!(v >= 0.0) || std::isinf(v)) return false;
-                }
-            }
-    }
-    return true;
-}
-
-struct Layout {
-    int64_t n = 0;
-    int dim = 2, s = 8;
-    bool copy_g = false;
-    int grid = 8, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_y = 16, tile_z = 16;
-    size_t off_g64 = 0, off_P = 0, off_dl = 0, off_mask = 0, off_gT = 0, off_invd = 0, off_vec = 0,
-           off_part = 0, off_scal = 0, off_cnt = 0, total = 0;
+// ------------------------------------------------------------------ scheduler state
+struct Sched {
+    std::deque<Net *> waiting;       // submitted; waiting for memory or a control slot
+    std::vector<Net *> preparing;    // setup enqueued; counters not yet on the host
+    std::vector<Net *> finishing;    // outputs enqueued; waiting for their copies
+    std::map<uint64_t, Net *> all;   // submitted through rn_submit and not yet collected
+    uint64_t next_ticket = 1;
 };
 
-Layout make_layout(const rn_problem *p, const rn_opts *o, int tile_y, int tile_z)
+std::mutex g_sched_mu;
+std::map<const rn_ctx *, Sched *> g_sched;
+
+Sched *sched_of(const rn_ctx *ctx)
 {
-    Layout L;
-    L.n = p->nx * p->ny * p->nz;
-    L.dim = p->dim;
-    L.s = (o && o->precision == RN_MIXED) ? 4 : 8;
-    L.copy_g = p->mem == RN_MEM_HOST;
-    L.tile_y = tile_y;
-    L.tile_z = tile_z;
-    if (p->dim == 2) {
-        L.ntx = div_up((int)p->nx, kWave);
-        L.nty = div_up((int)p->ny, L.s == 4 ? kTY2f : kTY2d);
-        L.ntz = 1;
-        L.ntiles = L.ntx * L.nty;
-        L.grid = div_up(L.ntiles, kBlock / kWave);
-    } else {
-        L.ntx = div_up((int)p->nx, kTX);
-        L.nty = div_up((int)p->ny, kTY);
-        L.ntz = div_up((int)p->nz, tile_z);
-        L.ntiles = L.ntx * L.nty * L.ntz;
-        L.grid = L.ntiles;
-    }
-    L.grid = (L.grid + 7) / 8 * 8;
-    const size_t n = (size_t)L.n;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        size_t o_ = off;
-        off += align256(bytes);
-        return o_;
-    };
-    L.off_g64 = take(L.copy_g ? (size_t)8 * L.dim * n : 0);
-    L.off_P = take(16 * n);
-    L.off_dl = take(8 * n);
-    L.off_mask = take(n);
-    L.off_gT = take((size_t)L.s * L.dim * n);
-    L.off_invd = take((size_t)L.s * n);
-    L.off_vec = take((size_t)6 * L.s * n);   // two sets of r, p, q; labels (8 bytes/node) alias here
-    L.off_part = take((size_t)L.grid * kRed * 8);
-    L.off_scal = take(sizeof(Scalars));
-    L.off_cnt = take(4 * sizeof(unsigned long long));
-    L.total = off;
-    return L;
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    auto it = g_sched.find(ctx);
+    return it == g_sched.end() ? nullptr : it->second;
 }
 
-int ensure_arena(rn_ctx *ctx, size_t bytes)
+void fail_net(Net *net, int status)
 {
-    if (bytes > ctx->budget) return RN_ENOMEM;
-    if (ctx->arena_bytes >= bytes) return RN_OK;
-    if (ctx->arena) {
-        RN_TRY(hipStreamSynchronize(ctx->stream));
-        RN_TRY(hipFree(ctx->arena));
-        ctx->arena = nullptr;
-        ctx->arena_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&ctx->arena, bytes);
-    if (e == hipErrorOutOfMemory) {
-        (void)hipGetLastError();
-        ctx->arena = nullptr;
-        return RN_ENOMEM;
-    }
-    RN_TRY(e);
-    ctx->arena_bytes = bytes;
-    return RN_OK;
+    net->status = status;
+    std::memset(&net->res, 0, sizeof(net->res));
+    net->res.status = status;
+    net->phase = NET_DONE;
 }
 
-double ev_seconds(hipEvent_t a, hipEvent_t b)
+double elapsed(hipEvent_t a, hipEvent_t b)
 {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    if (!a || !b || hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
     return ms * 1e-3;
 }
 
-// Upload (or borrow) conductances, validate device-resident ones, build the
-// mask, Jacobi scale and initial field. Fills *n_live.
-int prepare(rn_ctx *ctx, const rn_problem *p, const Layout &L, const double *gd[3], int64_t *n_live,
-            bool want_mask_buffer)
+// One scheduling step; the caller holds ctx->call_mu. Returns RN_OK or RN_EDEVICE.
+int tick(rn_ctx *ctx, Sched *S, bool *progressed)
 {
-    char *base = (char *)ctx->arena;
-    const size_t n = (size_t)L.n;
-    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
-    unsigned long long *cnt = (unsigned long long *)(base + L.off_cnt);
-    gd[0] = gd[1] = gd[2] = nullptr;
-    if (L.copy_g) {
-        for (int k = 0; k < p->dim; ++k) {
-            double *dst = (double *)(base + L.off_g64) + (size_t)k * n;
-            RN_TRY(hipMemcpyAsync(dst, p->g[k], 8 * n, hipMemcpyHostToDevice, ctx->stream));
-            gd[k] = dst;
+    *progressed = false;
+    hipStream_t st = ctx->stream;
+    // 1. admit waiting networks while memory and control slots allow
+    while (!S->waiting.empty() && !ctx->engine.full()) {
+        Net *net = S->waiting.front();
+        hipError_t he;
+        void *p = ctx->pool.alloc(net->L.total, &he);
+        if (!p) {
+            if (he != hipSuccess) {              // the device itself is out of memory
+                S->waiting.pop_front();
+                fail_net(net, RN_ENOMEM);
+                *progressed = true;
+                continue;
+            }
+            break;                               // wait until a running network frees memory
+        }
+        S->waiting.pop_front();
+        net->base = (char *)p;
+        int r = ctx->engine.prepare(net, st, &ctx->err);
+        if (r) return r;
+        S->preparing.push_back(net);
+        *progressed = true;
+    }
+    // 2. prepared networks: activate them (or finish them at once)
+    for (size_t i = 0; i < S->preparing.size();) {
+        Net *net = S->preparing[i];
+        const hipError_t q = hipEventQuery(net->ev);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        RN_TRY(q);
+        S->preparing.erase(S->preparing.begin() + i);
+        int r = ctx->engine.after_prepare(net, st, &ctx->err);
+        if (r == RN_EDEVICE) return r;
+        if (net->phase == NET_FINISHING) S->finishing.push_back(net);
+        if (net->phase == NET_DONE) {           // invalid values: nothing was written
+            ctx->pool.free(net->base);
+            net->base = nullptr;
+        }
+        *progressed = true;
+    }
+    // 3. one chunk of pass rounds for every active network
+    std::vector<Net *> fin;
+    if (ctx->engine.active_count() > 0) {
+        int r = ctx->engine.launch_chunk(ctx->engine.next_chunk(), st, &ctx->err);
+        if (r) return r;
+        r = ctx->engine.collect(&fin, false, st, &ctx->err);
+        if (r) return r;
+        *progressed = true;
+    } else if (ctx->engine.outstanding() > 0) {
+        int r = ctx->engine.collect(&fin, true, st, &ctx->err);
+        if (r) return r;
+        *progressed = true;
+    }
+    for (Net *n : fin) S->finishing.push_back(n);
+    // 4. finished networks whose outputs have landed: release their memory
+    for (size_t i = 0; i < S->finishing.size();) {
+        Net *net = S->finishing[i];
+        const hipError_t q = hipEventQuery(net->ev);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        RN_TRY(q);
+        S->finishing.erase(S->finishing.begin() + i);
+        ctx->pool.free(net->base);
+        net->base = nullptr;
+        net->res.t_mask_s = elapsed(net->ev_a, net->ev_b);
+        net->res.t_loop_s = elapsed(net->ev_c, net->ev_d);
+        net->res.t_total_s = now_s() - net->t_start;
+        net->phase = NET_DONE;
+        *progressed = true;
+    }
+    return RN_OK;
+}
+
+bool busy(const rn_ctx *ctx, const Sched *S)
+{
+    return !S->waiting.empty() || !S->preparing.empty() || !S->finishing.empty() ||
+           ctx->engine.active_count() > 0 || ctx->engine.outstanding() > 0;
+}
+
+// Block while nothing can progress (only setup or output copies in flight).
+void idle_wait(Sched *S)
+{
+    if (!S->preparing.empty()) (void)hipEventSynchronize(S->preparing.front()->ev);
+    else if (!S->finishing.empty()) (void)hipEventSynchronize(S->finishing.front()->ev);
+    else std::this_thread::sleep_for(std::chrono::microseconds(50));
+}
+
+// A network record (validated, laid out) for the scheduler.
+int make_net(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, Net **out)
+{
+    int st = check_shape(p);
+    if (st) return st;
+    rn_opts o;
+    if (opts) o = *opts;
+    else rn_opts_default(&o);
+    if ((st = check_opts(&o))) return st;
+    if (p->mem == RN_MEM_HOST && !host_values_ok(p)) return RN_EINVAL;
+    Net *net = new Net();
+    net->prob = *p;
+    net->opts = o;
+    net->L = make_layout(p, &o);
+    if (net->L.total > ctx->pool.budget()) {
+        delete net;
+        return RN_ENOMEM;
+    }
+    net->t_start = now_s();
+    *out = net;
+    return RN_OK;
+}
+
+void release_net(Net *net)
+{
+    for (hipEvent_t e : {net->ev, net->ev_a, net->ev_b, net->ev_c, net->ev_d})
+        if (e) (void)hipEventDestroy(e);
+    delete net;
+}
+
+// Drive the scheduler on this thread until every listed network is done.
+int drive_until(rn_ctx *ctx, Sched *S, const std::vector<Net *> &nets)
+{
+    auto all_done = [&]() {
+        for (Net *n : nets)
+            if (n->phase != NET_DONE) return false;
+        return true;
+    };
+    while (!all_done()) {
+        bool prog = false;
+        int r = tick(ctx, S, &prog);
+        if (r) return r;
+        if (!prog) idle_wait(S);
+    }
+    return RN_OK;
+}
+
+void fail_all(rn_ctx *ctx, Sched *S, int status)
+{
+    ctx->engine.abort_all();
+    for (Net *n : S->waiting) fail_net(n, status);
+    for (Net *n : S->preparing) fail_net(n, status);
+    for (Net *n : S->finishing) fail_net(n, status);
+    for (auto &kv : S->all)
+        if (kv.second->phase != NET_DONE) fail_net(kv.second, status);
+    S->waiting.clear();
+    S->preparing.clear();
+    S->finishing.clear();
+}
+
+// Lock held by an API call; the server thread yields the context to it.
+struct CallLock {
+    rn_ctx *ctx;
+    std::unique_lock<std::mutex> lk;
+    explicit CallLock(rn_ctx *c) : ctx(c)
+    {
+        ctx->callers.fetch_add(1);
+        lk = std::unique_lock<std::mutex>(ctx->call_mu);
+        ctx->callers.fetch_sub(1);
+    }
+};
+
+void server_main(rn_ctx *ctx)
+{
+    Sched *S = sched_of(ctx);
+    (void)hipSetDevice(ctx->device);
+    std::unique_lock<std::mutex> lk(ctx->call_mu);
+    bool broken = false;
+    while (!ctx->server->stop) {
+        if (broken || !busy(ctx, S)) {
+            ctx->server->cv.wait_for(lk, std::chrono::milliseconds(20));
+            if (broken) fail_all(ctx, S, RN_EDEVICE);
+            continue;
+        }
+        bool prog = false;
+        if (tick(ctx, S, &prog)) {
+            // a device error fails every network in flight; the context is unusable
+            broken = true;
+            fail_all(ctx, S, RN_EDEVICE);
+            continue;
+        }
+        if (!prog) {
+            lk.unlock();
+            idle_wait(S);
+            lk.lock();
+        } else if (ctx->callers.load() > 0) {
+            // let submitters and pollers in between chunks
+            lk.unlock();
+            for (int spin = 0; spin < 1000 && ctx->callers.load() > 0; ++spin)
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
+            lk.lock();
+        }
+    }
+}
+
+int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opts *opts, int32_t n_opts,
+               rn_result *out)
+{
+    if (!ctx || !out || !probs || count < 1) return RN_EINVAL;
+    if (!(n_opts == 0 || n_opts == 1 || n_opts == count)) return RN_EINVAL;
+    if (n_opts > 0 && !opts) return RN_EINVAL;
+    std::vector<Net *> nets((size_t)count, nullptr);
+    for (int i = 0; i < count; ++i) {
+        const rn_opts *o = n_opts == 0 ? nullptr : (n_opts == 1 ? opts : opts + i);
+        int st = make_net(ctx, probs + i, o, &nets[i]);
+        if (st) {
+            for (Net *n : nets)
+                if (n) release_net(n);
+            return st;
+        }
+    }
+    Sched *S = sched_of(ctx);
+    int r = RN_OK;
+    if (ctx->server) {
+        // the server thread drives: hand the networks over and wait for them
+        {
+            CallLock cl(ctx);
+            for (Net *n : nets) S->waiting.push_back(n);
+        }
+        ctx->server->cv.notify_all();
+        while (true) {
+            std::this_thread::sleep_for(std::chrono::microseconds(200));
+            CallLock cl(ctx);
+            bool all_done = true;
+            for (Net *n : nets) all_done = all_done && n->phase == NET_DONE;
+            if (all_done) break;
         }
     } else {
-        for (int k = 0; k < p->dim; ++k) gd[k] = p->g[k];
-    }
-    RN_TRY(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), ctx->stream));
-    if (!L.copy_g) {
-        RN_TRY(launch_validate(lat, gd, cnt + 1, ctx->stream));
-    }
-    int *parent = (int *)(base + L.off_vec);
-    unsigned *flags = (unsigned *)(base + L.off_vec + 4 * n);
-    uint8_t *mask = want_mask_buffer ? (uint8_t *)(base + L.off_mask) : nullptr;
-    double *dl = (double *)(base + L.off_dl);
-    double *P0 = (double *)(base + L.off_P);
-    RN_TRY(launch_mask(lat, gd, parent, flags, mask, dl, P0, cnt, ctx->stream));
-    RN_TRY(hipMemcpyAsync(ctx->host_cnt, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream));
-    RN_TRY(hipStreamSynchronize(ctx->stream));
-    if (ctx->host_cnt[1] != 0) return RN_EINVAL;
-    *n_live = (int64_t)ctx->host_cnt[0];
-    return RN_OK;
-}
-
-int copy_out(rn_ctx *ctx, void *dst, const void *src, size_t bytes, int mem)
-{
-    RN_TRY(hipMemcpyAsync(dst, src, bytes, mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
-                          ctx->stream));
-    return RN_OK;
-}
-
-template <typename T>
-int run_loop(rn_ctx *ctx, const rn_problem *p, const rn_opts *o, const Layout &L, const double *const gd[3],
-             Scalars *hs)
-{
-    char *base = (char *)ctx->arena;
-    const size_t n = (size_t)L.n;
-    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
-    T *gT[3] = {nullptr, nullptr, nullptr};
-    for (int k = 0; k < p->dim; ++k) gT[k] = (T *)(base + L.off_gT) + (size_t)k * n;
-    T *invd = (T *)(base + L.off_invd);
-    T *vec = (T *)(base + L.off_vec);
-    RN_TRY(launch_scale<T>(lat, gd, (const double *)(base + L.off_dl), gT, invd, vec, (int64_t)(6 * n),
-                           ctx->stream));
-
-    Scalars *ds = (Scalars *)(base + L.off_scal);
-    Scalars init;
-    std::memset(&init, 0, sizeof(init));
-    init.mode = MODE_REFRESH;
-    init.first = 1;
-    init.fp32 = L.s == 4;
-    init.max_iter = o->max_iter;
-    init.sigma = 1.0;
-    init.sigma_next = 1.0;
-    init.tol = o->tol;
-    init.delta = (L.s == 4) ? (o->delta > 0.0 ? o->delta : 0.1) : 0.0;
-    init.kappa = 1.0;
-    init.bhat = 1.0;
-    init.last_check = INFINITY;
-    ctx->host_scal[2] = init;
-    RN_TRY(hipMemcpyAsync(ds, &ctx->host_scal[2], sizeof(Scalars), hipMemcpyHostToDevice, ctx->stream));
-
-    PassArgs<T> a[2];
-    for (int par = 0; par < 2; ++par) {
-        PassArgs<T> &A = a[par];
-        std::memset(&A, 0, sizeof(A));
-        A.nx = (int)p->nx;
-        A.ny = (int)p->ny;
-        A.nz = (int)p->nz;
-        A.axis = p->axis;
-        A.ntx = L.ntx;
-        A.nty = L.nty;
-        A.ntz = L.ntz;
-        A.tile_y = L.tile_y;
-        A.tile_z = L.tile_z;
-        A.ntiles = L.ntiles;
-        A.grid = L.grid;
-        for (int k = 0; k < 3; ++k) {
-            A.g64[k] = gd[k];
-            A.gT[k] = gT[k];
+        std::lock_guard<std::mutex> lk(ctx->call_mu);
+        if (hipSetDevice(ctx->device) != hipSuccess) return RN_EDEVICE;
+        for (Net *n : nets) S->waiting.push_back(n);
+        r = drive_until(ctx, S, nets);
+        if (r) {
+            fail_all(ctx, S, r);
+            (void)hipStreamSynchronize(ctx->stream);
         }
-        A.P[0] = (double *)(base + L.off_P);
-        A.P[1] = A.P[0] + n;
-        A.invd = invd;
-        VecSet<T> s0{vec, vec + n, vec + 2 * n};
-        VecSet<T> s1{vec + 3 * n, vec + 4 * n, vec + 5 * n};
-        A.src = par == 0 ? s0 : s1;
-        A.dst = par == 0 ? s1 : s0;
-        A.partials = (double *)(base + L.off_part);
-        A.s = ds;
     }
-
-    RN_TRY(hipEventRecord(ctx->ev_t[2], ctx->stream));
-    const int64_t hard_cap = 2 * o->max_iter + 256;
-    int64_t launched = 0;
-    int chunk = 16;
-    int pending = -1, slot = 0;
-    double prev_est = -1.0;
-    int64_t prev_iters = 0;
-    int last_chunk = 0;
-    while (launched < hard_cap) {
-        const int c = (int)std::min<int64_t>(chunk, hard_cap - launched);
-        for (int i = 0; i < c; ++i) {
-            RN_TRY(launch_pass<T>(p->dim, a[launched & 1], ctx->stream));
-            ++launched;
-        }
-        RN_TRY(hipMemcpyAsync(&ctx->host_scal[slot], ds, sizeof(Scalars), hipMemcpyDeviceToHost, ctx->stream));
-        RN_TRY(hipEventRecord(ctx->ev_chunk[slot], ctx->stream));
-        if (pending >= 0) {
-            RN_TRY(hipEventSynchronize(ctx->ev_chunk[pending]));
-            const Scalars &h = ctx->host_scal[pending];
-            if (h.mode == MODE_DONE) break;
-            // size the next chunk from the observed convergence rate; the
-            // chunk enqueued last is still in flight, and launches left over
-            // after convergence are idle, so aim slightly short
-            int next = std::min(chunk * 2, 256);
-            if (prev_est > 0.0 && h.est_rel > 0.0 && h.est_rel < prev_est && h.iters > prev_iters) {
-                const double rate = std::log(prev_est / h.est_rel) / (double)(h.iters - prev_iters);
-                const double remain = std::log(std::max(h.est_rel / o->tol, 1.0)) / rate;
-                const double want = 0.9 * remain - (double)last_chunk;
-                next = (int)std::min(256.0, std::max(8.0, want));
-            }
-            prev_est = h.est_rel;
-            prev_iters = h.iters;
-            chunk = next;
-        }
-        last_chunk = c;
-        pending = slot;
-        slot ^= 1;
+    int first = RN_OK;
+    for (int i = 0; i < count; ++i) {
+        if (!r) out[i] = nets[i]->res;
+        if (nets[i]->status != RN_OK && first == RN_OK) first = nets[i]->status;
+        if (nets[i]->base) ctx->pool.free(nets[i]->base);
+        release_net(nets[i]);
     }
-    RN_TRY(hipEventRecord(ctx->ev_t[3], ctx->stream));
-    RN_TRY(hipMemcpyAsync(hs, ds, sizeof(Scalars), hipMemcpyDeviceToHost, ctx->stream));
-    RN_TRY(hipStreamSynchronize(ctx->stream));
-    hs->passes = launched;   // report launches (the device counts only working passes)
-    return RN_OK;
-}
-
-double cross_section(const rn_problem *p)
-{
-    double s = 1.0;
-    const int64_t n[3] = {p->nx, p->ny, p->nz};
-    for (int k = 0; k < p->dim; ++k)
-        if (k != p->axis) s *= (double)n[k];
-    return s;
+    return r ? r : first;
 }
 
 }  // namespace
 
 extern "C" {
 
-int rn_version(void) { return 100; }
+int rn_version(void) { return 101; }
 
 const char *rn_strerror(int status)
 {
@@ -373,27 +353,23 @@ int rn_create(int device, size_t budget, rn_ctx **out)
     if (device < 0 || device >= count) return RN_EINVAL;
     rn_ctx *ctx = new rn_ctx();
     ctx->device = device;
-    auto fail = [&](hipError_t e) {
-        (void)e;
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched[ctx] = new Sched();
+    }
+    auto fail = [&]() {
         rn_destroy(ctx);
         return RN_EDEVICE;
     };
-    hipError_t e = hipSetDevice(device);
-    if (e != hipSuccess) return fail(e);
+    if (hipSetDevice(device) != hipSuccess) return fail();
     size_t free_b = 0, total_b = 0;
-    if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return fail(e);
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail();
     ctx->budget = budget ? budget : (size_t)(0.9 * (double)free_b);
-    if ((e = hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking)) != hipSuccess) return fail(e);
+    ctx->pool.set_budget(ctx->budget);
+    if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) return fail();
     ctx->stream = ctx->own;
-    if ((e = hipHostMalloc((void **)&ctx->host_scal, 3 * sizeof(Scalars), hipHostMallocDefault)) != hipSuccess)
-        return fail(e);
-    if ((e = hipHostMalloc((void **)&ctx->host_cnt, 4 * sizeof(unsigned long long), hipHostMallocDefault)) !=
-        hipSuccess)
-        return fail(e);
-    for (auto &ev : ctx->ev_chunk)
-        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return fail(e);
-    for (auto &ev : ctx->ev_t)
-        if ((e = hipEventCreate(&ev)) != hipSuccess) return fail(e);
+    if (ctx->engine.init(ctx->stream, &ctx->err)) return fail();
+    ctx->engine_ok = true;
     *out = ctx;
     return RN_OK;
 }
@@ -401,15 +377,33 @@ int rn_create(int device, size_t budget, rn_ctx **out)
 int rn_destroy(rn_ctx *ctx)
 {
     if (!ctx) return RN_OK;
+    if (ctx->server) {
+        {
+            std::lock_guard<std::mutex> lk(ctx->call_mu);
+            ctx->server->stop = true;
+        }
+        ctx->server->cv.notify_all();
+        if (ctx->server->th.joinable()) ctx->server->th.join();
+        delete ctx->server;
+        ctx->server = nullptr;
+    }
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->arena) (void)hipFree(ctx->arena);
-    if (ctx->host_scal) (void)hipHostFree(ctx->host_scal);
-    if (ctx->host_cnt) (void)hipHostFree(ctx->host_cnt);
-    for (auto ev : ctx->ev_chunk)
-        if (ev) (void)hipEventDestroy(ev);
-    for (auto ev : ctx->ev_t)
-        if (ev) (void)hipEventDestroy(ev);
+    Sched *S = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        auto it = g_sched.find(ctx);
+        if (it != g_sched.end()) {
+            S = it->second;
+            g_sched.erase(it);
+        }
+    }
+    if (S) {
+        for (auto &kv : S->all) release_net(kv.second);
+        delete S;
+    }
+    if (ctx->engine_ok) ctx->engine.destroy();
+    ctx->pool.release_all();
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
     delete ctx;
     return RN_OK;
@@ -418,6 +412,8 @@ int rn_destroy(rn_ctx *ctx)
 int rn_set_stream(rn_ctx *ctx, void *stream)
 {
     if (!ctx) return RN_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    if (ctx->server) return RN_EINVAL;        // the server owns the stream once started
     ctx->stream = stream ? (hipStream_t)stream : ctx->own;
     return RN_OK;
 }
@@ -441,7 +437,7 @@ size_t rn_footprint(const rn_problem *p, const rn_opts *o)
     if (check_shape(p) != RN_OK) return 0;
     rn_opts d;
     rn_opts_default(&d);
-    return make_layout(p, o ? o : &d, 16, 16).total;
+    return make_layout(p, o ? o : &d).total;
 }
 
 int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
@@ -451,89 +447,119 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
     if (st) return st;
     if (!p->mask_out) return RN_EINVAL;
     if (p->mem == RN_MEM_HOST && !host_values_ok(p)) return RN_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    if (ctx->server) return RN_EINVAL;        // the server owns the stream once started
     RN_TRY(hipSetDevice(ctx->device));
-    rn_opts o;
-    rn_opts_default(&o);
-    o.precision = RN_MIXED;   // smallest layout: the mask needs no FP64 CG state
-    Layout L = make_layout(p, &o, ctx->tile_y, ctx->tile_z);
-    if ((st = ensure_arena(ctx, L.total))) return st;
-    const double *gd[3];
-    int64_t n_live = 0;
-    if ((st = prepare(ctx, p, L, gd, &n_live, true))) return st;
-    if ((st = copy_out(ctx, p->mask_out, (char *)ctx->arena + L.off_mask, (size_t)L.n, p->mem))) return st;
-    RN_TRY(hipStreamSynchronize(ctx->stream));
-    if (n_live_out) *n_live_out = n_live;
-    return RN_OK;
+    // the mask needs the FP64 bonds (host input), the field and diagonal
+    // scratch, the mask, 8 bytes of labels per node and the counters
+    const size_t n = (size_t)(p->nx * p->ny * p->nz);
+    auto a256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const bool copy_g = p->mem == RN_MEM_HOST;
+    const size_t off_g = 0, off_P = off_g + a256(copy_g ? 8 * p->dim * n : 0), off_dl = off_P + a256(8 * n),
+                 off_mask = off_dl + a256(8 * n), off_lab = off_mask + a256(n), off_cnt = off_lab + a256(8 * n),
+                 total = off_cnt + 256;
+    hipError_t he;
+    char *base = (char *)ctx->pool.alloc(total, &he);
+    if (!base) return RN_ENOMEM;
+    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, (int64_t)n};
+    const double *gd[3] = {nullptr, nullptr, nullptr};
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->pool.free(base);
+        return r;
+    };
+    if (copy_g) {
+        for (int k = 0; k < p->dim; ++k) {
+            double *dst = (double *)(base + off_g) + (size_t)k * n;
+            if (hipMemcpyAsync(dst, p->g[k], 8 * n, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+                return done(RN_EDEVICE);
+            gd[k] = dst;
+        }
+    } else {
+        for (int k = 0; k < p->dim; ++k) gd[k] = p->g[k];
+    }
+    unsigned long long *cnt = (unsigned long long *)(base + off_cnt);
+    unsigned long long hc[4] = {0, 0, 0, 0};
+    if (hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (!copy_g && launch_validate(lat, gd, cnt + 1, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (launch_mask(lat, gd, (int *)(base + off_lab), (unsigned *)(base + off_lab + 4 * n),
+                    (uint8_t *)(base + off_mask), (double *)(base + off_dl), (double *)(base + off_P), cnt,
+                    ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    if (hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (hc[1] != 0) return done(RN_EINVAL);
+    if (hipMemcpyAsync(p->mask_out, base + off_mask, n,
+                       p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    if (n_live_out) *n_live_out = (int64_t)hc[0];
+    return done(RN_OK);
 }
 
 int rn_solve(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, rn_result *out)
 {
-    const auto t0 = std::chrono::steady_clock::now();
     if (!ctx || !out) return RN_EINVAL;
-    int st = check_shape(p);
+    return solve_many(ctx, 1, p, opts, opts ? 1 : 0, out);
+}
+
+int rn_solve_batch(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opts *opts, int32_t n_opts,
+                   rn_result *out)
+{
+    return solve_many(ctx, count, probs, opts, n_opts, out);
+}
+
+int rn_submit(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, uint64_t *ticket_out)
+{
+    if (!ctx || !ticket_out) return RN_EINVAL;
+    Net *net = nullptr;
+    int st = make_net(ctx, p, opts, &net);
     if (st) return st;
-    rn_opts o;
-    if (opts) o = *opts;
-    else rn_opts_default(&o);
-    if ((st = check_opts(&o))) return st;
-    if (p->mem == RN_MEM_HOST && !host_values_ok(p)) return RN_EINVAL;
-    RN_TRY(hipSetDevice(ctx->device));
-    Layout L = make_layout(p, &o, ctx->tile_y, ctx->tile_z);
-    if ((st = ensure_arena(ctx, L.total))) return st;
-
-    RN_TRY(hipEventRecord(ctx->ev_t[0], ctx->stream));
-    const double *gd[3];
-    int64_t n_live = 0;
-    if ((st = prepare(ctx, p, L, gd, &n_live, true))) return st;
-    RN_TRY(hipEventRecord(ctx->ev_t[1], ctx->stream));
-
-    rn_result r;
-    std::memset(&r, 0, sizeof(r));
-    r.n_live = n_live;
-    char *base = (char *)ctx->arena;
-    const double *P_final = (const double *)(base + L.off_P);
-    const int64_t na = p->axis == 0 ? p->nx : (p->axis == 1 ? p->ny : p->nz);
-    if (n_live == 0) {
-        double G = 0.0;
-        if (na == 2) {
-            Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
-            double *dG = (double *)(base + L.off_cnt) + 2;
-            RN_TRY(launch_direct_flux(lat, gd[p->axis], dG, ctx->stream));
-            RN_TRY(hipMemcpyAsync(&ctx->host_scal[2].Q_in, dG, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-            RN_TRY(hipStreamSynchronize(ctx->stream));
-            G = ctx->host_scal[2].Q_in;
-        }
-        r.status = RN_OK;
-        r.converged = 1;
-        r.Q_in = r.Q_out = r.G = G;
-        r.K = G * (double)(na - 1) / cross_section(p);
-        RN_TRY(hipEventRecord(ctx->ev_t[2], ctx->stream));
-        RN_TRY(hipEventRecord(ctx->ev_t[3], ctx->stream));
-    } else {
-        Scalars hs;
-        st = (L.s == 4) ? run_loop<float>(ctx, p, &o, L, gd, &hs) : run_loop<double>(ctx, p, &o, L, gd, &hs);
-        if (st) return st;
-        P_final = (const double *)(base + L.off_P) + (size_t)(hs.refreshes & 1) * (size_t)L.n;
-        r.status = hs.status;
-        r.converged = hs.converged;
-        r.Q_in = hs.Q_in;
-        r.Q_out = hs.Q_out;
-        r.G = hs.Q_in - hs.xr;
-        r.K = r.G * (double)(na - 1) / cross_section(p);
-        r.rel_resid = hs.rel_resid;
-        r.iters = hs.iters;
-        r.refreshes = hs.refreshes;
-        r.passes = hs.passes;
-        if (r.status == 0 && !r.converged) r.status = RN_ENOCONV;
+    Sched *S = sched_of(ctx);
+    CallLock cl(ctx);
+    if (!ctx->server) {
+        ctx->server = new rn_server();
+        ctx->server->th = std::thread(server_main, ctx);
     }
-    if (p->p_out && (st = copy_out(ctx, p->p_out, P_final, 8 * (size_t)L.n, p->mem))) return st;
-    if (p->mask_out && (st = copy_out(ctx, p->mask_out, base + L.off_mask, (size_t)L.n, p->mem))) return st;
-    RN_TRY(hipStreamSynchronize(ctx->stream));
-    r.t_mask_s = ev_seconds(ctx->ev_t[0], ctx->ev_t[1]);
-    r.t_loop_s = ev_seconds(ctx->ev_t[2], ctx->ev_t[3]);
-    r.t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    *out = r;
-    return r.status;
+    net->ticket = S->next_ticket++;
+    S->all[net->ticket] = net;
+    S->waiting.push_back(net);
+    *ticket_out = net->ticket;
+    ctx->server->cv.notify_all();
+    return RN_OK;
+}
+
+int rn_poll(rn_ctx *ctx, uint64_t ticket, rn_result *out)
+{
+    if (!ctx || !out) return RN_EINVAL;
+    Sched *S = sched_of(ctx);
+    CallLock cl(ctx);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return RN_ENOTFOUND;
+    Net *net = it->second;
+    if (net->phase != NET_DONE) return RN_EAGAIN;
+    *out = net->res;
+    const int st = net->status;
+    S->all.erase(it);
+    release_net(net);
+    return st;
+}
+
+int rn_stats(rn_ctx *ctx, rn_stats_t *out)
+{
+    if (!ctx || !out) return RN_EINVAL;
+    Sched *S = sched_of(ctx);
+    CallLock cl(ctx);
+    std::memset(out, 0, sizeof(*out));
+    out->waiting = (int64_t)S->waiting.size();
+    out->preparing = (int64_t)S->preparing.size();
+    out->active = ctx->engine.active_count();
+    out->finishing = (int64_t)S->finishing.size();
+    out->bytes_in_use = (int64_t)ctx->pool.in_use();
+    out->budget = (int64_t)ctx->pool.budget();
+    out->launches = ctx->engine.launches();
+    out->peak_active = ctx->engine.peak_active();
+    return RN_OK;
 }
 
 }  // extern "C"

@@ -71,7 +71,7 @@ struct PassArgs {
     int ntx, nty, ntz;           // tile counts
     int tile_y, tile_z;          // rows per 2D strip / planes per 3D tile
     int ntiles;                  // total tiles (2D: wave strips; 3D: workgroup tiles)
-    int grid;                    // workgroups launched (multiple of 8)
+    int grid;                    // workgroups of this network per pass (multiple of 8)
     // FP64 data
     const double *g64[3];        // original conductances
     double *P[2];                // full FP64 pressure field: CG passes after refresh m add their
@@ -98,8 +98,12 @@ template <typename T>
 hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dlive, T *const gT[3], T *invd,
                         T *vec, int64_t nvec, hipStream_t st);
 hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
+// One pass of every network in the block table blk[0..nblocks): entry
+// (network, local block); tab[2 * network + parity] are that network's
+// arguments and scal[network] its control block.
 template <typename T>
-hipError_t launch_pass(int dim, const PassArgs<T> &a, hipStream_t st);
+hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
+                       hipStream_t st);
 
 // tile geometry of the pass kernels: 2D tiles are 64 x kTY2f (FP32) or
 // 64 x kTY2d (FP64) per wave, 3D tiles 64 x kTY x tile_z per workgroup

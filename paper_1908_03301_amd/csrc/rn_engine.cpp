@@ -1,0 +1,575 @@
+// rn_engine.cpp -- device memory pool, per-network lifecycle and the
+// multi-network iteration engine.
+//
+// Every network in the engine owns a control-block slot. Each pass round
+// launches one pass kernel per kind (2D/3D x FP32/FP64) over a block table
+// listing (slot, local block) for every active network, so networks of any
+// size and dimension advance together while each keeps its own reduction,
+// scalars and convergence. A network's arithmetic depends only on its own
+// data and tile shape, never on the rest of the launch: a network gives the
+// same bits alone and in a batch.
+#include "rn_runtime.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace rn {
+
+#define ENG_TRY(expr)                                                  \
+    do {                                                               \
+        hipError_t e_ = (expr);                                        \
+        if (e_ != hipSuccess) {                                        \
+            if (err) *err = std::string(#expr) + ": " + hipGetErrorString(e_); \
+            return RN_EDEVICE;                                         \
+        }                                                              \
+    } while (0)
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ------------------------------------------------------------------ checks
+
+int check_shape(const rn_problem *p)
+{
+    if (!p) return RN_EINVAL;
+    if (p->dim != 2 && p->dim != 3) return RN_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return RN_EINVAL;
+    if (p->dim == 2 && p->nz != 1) return RN_EINVAL;
+    if (p->axis < 0 || p->axis >= p->dim) return RN_EINVAL;
+    const int64_t na = p->axis == 0 ? p->nx : (p->axis == 1 ? p->ny : p->nz);
+    if (na < 2) return RN_EINVAL;
+    if (p->nx > INT32_MAX || p->ny > INT32_MAX || p->nz > INT32_MAX) return RN_EINVAL;
+    const double n = (double)p->nx * (double)p->ny * (double)p->nz;
+    if (n >= 2147483647.0) return RN_EINVAL;
+    if (p->mem != RN_MEM_HOST && p->mem != RN_MEM_DEVICE) return RN_EINVAL;
+    if (p->reserved != 0) return RN_EINVAL;
+    for (int k = 0; k < p->dim; ++k)
+        if (!p->g[k]) return RN_EINVAL;
+    if (p->dim == 2 && p->g[2]) return RN_EINVAL;
+    return RN_OK;
+}
+
+int check_opts(const rn_opts *o)
+{
+    if (!o) return RN_EINVAL;
+    if (o->precision != RN_FP64 && o->precision != RN_MIXED) return RN_EINVAL;
+    if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RN_EINVAL;
+    if (o->max_iter < 0) return RN_EINVAL;
+    if (!(o->delta >= 0.0) || o->delta >= 1.0) return RN_EINVAL;
+    if (o->reserved != 0) return RN_EINVAL;
+    return RN_OK;
+}
+
+bool host_values_ok(const rn_problem *p)
+{
+    const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+    for (int k = 0; k < p->dim; ++k) {
+        const double *g = p->g[k];
+        for (int64_t z = 0; z < nz; ++z)
+            for (int64_t y = 0; y < ny; ++y) {
+                const double *row = g + nx * (y + ny * z);
+                int64_t xe = nx;
+                if (k == 0) xe = nx - 1;
+                else if (k == 1 && y == ny - 1) xe = 0;
+                else if (k == 2 && z == nz - 1) xe = 0;
+                for (int64_t x = 0; x < xe; ++x) {
+                    const double v = row[x];
+                    if (!(v >= 0.0) || std::isinf(v)) return false;
+                }
+            }
+    }
+    return true;
+}
+
+double cross_section(const rn_problem *p)
+{
+    double s = 1.0;
+    const int64_t n[3] = {p->nx, p->ny, p->nz};
+    for (int k = 0; k < p->dim; ++k)
+        if (k != p->axis) s *= (double)n[k];
+    return s;
+}
+
+Layout make_layout(const rn_problem *p, const rn_opts *o)
+{
+    Layout L;
+    L.n = p->nx * p->ny * p->nz;
+    L.dim = p->dim;
+    L.s = (o && o->precision == RN_MIXED) ? 4 : 8;
+    L.copy_g = p->mem == RN_MEM_HOST;
+    if (p->dim == 2) {
+        L.ntx = div_up((int)p->nx, kWave);
+        L.nty = div_up((int)p->ny, L.s == 4 ? kTY2f : kTY2d);
+        L.ntz = 1;
+        L.ntiles = L.ntx * L.nty;
+        L.grid = div_up(L.ntiles, kBlock / kWave);
+    } else {
+        L.tile_z = 16;
+        L.ntx = div_up((int)p->nx, kTX);
+        L.nty = div_up((int)p->ny, kTY);
+        L.ntz = div_up((int)p->nz, L.tile_z);
+        L.ntiles = L.ntx * L.nty * L.ntz;
+        L.grid = L.ntiles;
+    }
+    L.grid = (L.grid + 7) / 8 * 8;
+    const size_t n = (size_t)L.n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o_ = off;
+        off += align256(bytes);
+        return o_;
+    };
+    L.off_g64 = take(L.copy_g ? (size_t)8 * L.dim * n : 0);
+    L.off_P = take(16 * n);
+    L.off_dl = take(8 * n);
+    L.off_mask = take(n);
+    L.off_gT = take((size_t)L.s * L.dim * n);
+    L.off_invd = take((size_t)L.s * n);
+    L.off_vec = take((size_t)6 * L.s * n);   // two sets of r, p, q; labels (8 bytes/node) alias here
+    L.off_part = take((size_t)L.grid * kRed * 8);
+    L.off_cnt = take(4 * sizeof(unsigned long long));
+    L.total = off;
+    return L;
+}
+
+// ------------------------------------------------------------------ pool
+
+Pool::~Pool() { release_all(); }
+
+void Pool::release_all()
+{
+    for (auto &s : slabs_) (void)hipFree(s.base);
+    slabs_.clear();
+    reserved_ = in_use_ = 0;
+}
+
+void *Pool::alloc(size_t bytes, hipError_t *err)
+{
+    *err = hipSuccess;
+    bytes = align256(bytes ? bytes : 256);
+    for (auto &s : slabs_) {
+        for (auto it = s.free_.begin(); it != s.free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, len = it->second;
+            s.free_.erase(it);
+            if (len > bytes) s.free_[off + bytes] = len - bytes;
+            s.used_[off] = bytes;
+            in_use_ += bytes;
+            return s.base + off;
+        }
+    }
+    const size_t gib = (size_t)1 << 30;
+    size_t size = std::max(bytes, gib);
+    if (reserved_ + size > budget_) size = bytes;
+    if (reserved_ + size > budget_) return nullptr;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, size);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *err = e;
+        return nullptr;
+    }
+    Slab s{(char *)p, size, {}, {}};
+    if (size > bytes) s.free_[bytes] = size - bytes;
+    s.used_[0] = bytes;
+    slabs_.push_back(std::move(s));
+    reserved_ += size;
+    in_use_ += bytes;
+    return p;
+}
+
+void Pool::free(void *ptr)
+{
+    if (!ptr) return;
+    char *p = (char *)ptr;
+    for (auto &s : slabs_) {
+        if (p < s.base || p >= s.base + s.size) continue;
+        const size_t off = (size_t)(p - s.base);
+        auto u = s.used_.find(off);
+        if (u == s.used_.end()) return;
+        size_t len = u->second;
+        s.used_.erase(u);
+        in_use_ -= len;
+        size_t start = off;
+        auto nx = s.free_.lower_bound(off);
+        if (nx != s.free_.end() && nx->first == off + len) {
+            len += nx->second;
+            s.free_.erase(nx);
+        }
+        auto pv = s.free_.lower_bound(off);
+        if (pv != s.free_.begin()) {
+            --pv;
+            if (pv->first + pv->second == off) {
+                start = pv->first;
+                len += pv->second;
+                s.free_.erase(pv);
+            }
+        }
+        s.free_[start] = len;
+        return;
+    }
+}
+
+// ------------------------------------------------------------------ engine
+
+int Engine::init(hipStream_t st, std::string *err)
+{
+    (void)st;
+    ENG_TRY(hipMalloc(&d_scal_, sizeof(Scalars) * kSlots));
+    ENG_TRY(hipMalloc(&d_tabf_, sizeof(PassArgs<float>) * 2 * kSlots));
+    ENG_TRY(hipMalloc(&d_tabd_, sizeof(PassArgs<double>) * 2 * kSlots));
+    for (int b = 0; b < 2; ++b) ENG_TRY(hipHostMalloc((void **)&h_scal_[b], sizeof(Scalars) * kSlots, hipHostMallocDefault));
+    ENG_TRY(hipHostMalloc((void **)&h_init_, sizeof(Scalars) * kSlots, hipHostMallocDefault));
+    ENG_TRY(hipHostMalloc((void **)&h_tabf_, sizeof(PassArgs<float>) * 2 * kSlots, hipHostMallocDefault));
+    ENG_TRY(hipHostMalloc((void **)&h_tabd_, sizeof(PassArgs<double>) * 2 * kSlots, hipHostMallocDefault));
+    ENG_TRY(hipHostMalloc((void **)&h_cnt_, sizeof(unsigned long long) * 4 * kSlots, hipHostMallocDefault));
+    for (auto &e : ev_chunk_) ENG_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    free_slots_.clear();
+    for (int s = kSlots - 1; s >= 0; --s) free_slots_.push_back(s);
+    return RN_OK;
+}
+
+void Engine::destroy()
+{
+    (void)hipFree(d_scal_);
+    (void)hipFree(d_tabf_);
+    (void)hipFree(d_tabd_);
+    for (auto p : h_scal_) (void)hipHostFree(p);
+    (void)hipHostFree(h_init_);
+    (void)hipHostFree(h_tabf_);
+    (void)hipHostFree(h_tabd_);
+    (void)hipHostFree(h_cnt_);
+    for (int k = 0; k < kKinds; ++k) {
+        (void)hipFree(d_blk_[k]);
+        (void)hipHostFree(h_blk_[k]);
+    }
+    for (auto e : ev_chunk_)
+        if (e) (void)hipEventDestroy(e);
+    d_scal_ = nullptr;
+}
+
+int Engine::prepare(Net *net, hipStream_t st, std::string *err)
+{
+    const rn_problem *p = &net->prob;
+    const Layout &L = net->L;
+    char *base = net->base;
+    const size_t n = (size_t)L.n;
+    net->slot = free_slots_.back();
+    free_slots_.pop_back();
+    by_slot_[net->slot] = net;
+    net->na = p->axis == 0 ? p->nx : (p->axis == 1 ? p->ny : p->nz);
+    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
+    unsigned long long *cnt = (unsigned long long *)(base + L.off_cnt);
+    if (!net->ev) ENG_TRY(hipEventCreateWithFlags(&net->ev, hipEventDisableTiming));
+    for (hipEvent_t *e : {&net->ev_a, &net->ev_b, &net->ev_c, &net->ev_d})
+        if (!*e) ENG_TRY(hipEventCreate(e));
+    ENG_TRY(hipEventRecord(net->ev_a, st));
+    if (L.copy_g) {
+        for (int k = 0; k < p->dim; ++k) {
+            double *dst = (double *)(base + L.off_g64) + (size_t)k * n;
+            ENG_TRY(hipMemcpyAsync(dst, p->g[k], 8 * n, hipMemcpyHostToDevice, st));
+            net->gd[k] = dst;
+        }
+    } else {
+        for (int k = 0; k < p->dim; ++k) net->gd[k] = p->g[k];
+    }
+    ENG_TRY(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), st));
+    if (!L.copy_g) ENG_TRY(launch_validate(lat, net->gd, cnt + 1, st));
+    int *parent = (int *)(base + L.off_vec);
+    unsigned *flags = (unsigned *)(base + L.off_vec + 4 * n);
+    ENG_TRY(launch_mask(lat, net->gd, parent, flags, (uint8_t *)(base + L.off_mask), (double *)(base + L.off_dl),
+                        (double *)(base + L.off_P), cnt, st));
+    if (net->na == 2) ENG_TRY(launch_direct_flux(lat, net->gd[p->axis], (double *)(cnt + 2), st));
+    ENG_TRY(hipEventRecord(net->ev_b, st));
+    ENG_TRY(hipMemcpyAsync(h_cnt_ + 4 * net->slot, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    ENG_TRY(hipEventRecord(net->ev, st));
+    net->phase = NET_PREPARING;
+    return RN_OK;
+}
+
+template <typename T>
+static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars *ds)
+{
+    const rn_problem *p = &net->prob;
+    const Layout &L = net->L;
+    char *base = net->base;
+    const size_t n = (size_t)L.n;
+    T *vec = (T *)(base + L.off_vec);
+    VecSet<T> s0{vec, vec + n, vec + 2 * n};
+    VecSet<T> s1{vec + 3 * n, vec + 4 * n, vec + 5 * n};
+    for (int k = 0; k < 2; ++k) {
+        PassArgs<T> A;
+        std::memset(&A, 0, sizeof(A));
+        A.nx = (int)p->nx;
+        A.ny = (int)p->ny;
+        A.nz = (int)p->nz;
+        A.axis = p->axis;
+        A.ntx = L.ntx;
+        A.nty = L.nty;
+        A.ntz = L.ntz;
+        A.tile_y = 0;
+        A.tile_z = L.tile_z;
+        A.ntiles = L.ntiles;
+        A.grid = L.grid;
+        for (int d = 0; d < 3; ++d) {
+            A.g64[d] = net->gd[d];
+            A.gT[d] = d < p->dim ? (const T *)(base + L.off_gT) + (size_t)d * n : nullptr;
+        }
+        A.P[0] = (double *)(base + L.off_P);
+        A.P[1] = A.P[0] + n;
+        A.invd = (const T *)(base + L.off_invd);
+        A.src = k == 0 ? s0 : s1;
+        A.dst = k == 0 ? s1 : s0;
+        A.partials = (double *)(base + L.off_part);
+        A.s = ds;
+        a2[(first_parity + k) & 1] = A;
+    }
+}
+
+int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
+{
+    const rn_problem *p = &net->prob;
+    const Layout &L = net->L;
+    char *base = net->base;
+    const size_t n = (size_t)L.n;
+    const unsigned long long *c = h_cnt_ + 4 * net->slot;
+    std::memset(&net->res, 0, sizeof(net->res));
+    if (c[1] != 0) {                                   // invalid device-resident values
+        net->status = RN_EINVAL;
+        net->res.status = RN_EINVAL;
+        by_slot_[net->slot] = nullptr;
+        free_slots_.push_back(net->slot);
+        net->slot = -1;
+        net->phase = NET_DONE;
+        return RN_EINVAL;
+    }
+    net->n_live = (int64_t)c[0];
+    net->res.n_live = net->n_live;
+    if (net->n_live == 0) {
+        double G = 0.0;
+        if (net->na == 2) std::memcpy(&G, &c[2], sizeof(double));
+        net->res.status = RN_OK;
+        net->res.converged = 1;
+        net->res.Q_in = net->res.Q_out = net->res.G = G;
+        net->res.K = G * (double)(net->na - 1) / cross_section(p);
+        net->status = RN_OK;
+        if (p->p_out)
+            ENG_TRY(hipMemcpyAsync(p->p_out, base + L.off_P, 8 * n,
+                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        if (p->mask_out)
+            ENG_TRY(hipMemcpyAsync(p->mask_out, base + L.off_mask, n,
+                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        ENG_TRY(hipEventRecord(net->ev_c, st));
+        ENG_TRY(hipEventRecord(net->ev_d, st));
+        ENG_TRY(hipEventRecord(net->ev, st));
+        by_slot_[net->slot] = nullptr;
+        free_slots_.push_back(net->slot);
+        net->slot = -1;
+        net->phase = NET_FINISHING;
+        return RN_OK;
+    }
+    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
+    const int slot = net->slot;
+    Scalars *ds = d_scal_ + slot;
+    Scalars &init = h_init_[slot];
+    std::memset(&init, 0, sizeof(init));
+    init.mode = MODE_REFRESH;
+    init.first = 1;
+    init.fp32 = L.s == 4;
+    init.max_iter = net->opts.max_iter;
+    init.sigma = 1.0;
+    init.sigma_next = 1.0;
+    init.tol = net->opts.tol;
+    init.delta = (L.s == 4) ? (net->opts.delta > 0.0 ? net->opts.delta : 0.1) : 0.0;
+    init.kappa = 1.0;
+    init.bhat = 1.0;
+    init.last_check = INFINITY;
+    const int par0 = (int)(rounds_ & 1);
+    if (L.s == 4) {
+        float *gT[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < p->dim; ++k) gT[k] = (float *)(base + L.off_gT) + (size_t)k * n;
+        ENG_TRY(launch_scale<float>(lat, net->gd, (const double *)(base + L.off_dl), gT,
+                                    (float *)(base + L.off_invd), (float *)(base + L.off_vec), (int64_t)(6 * n), st));
+        fill_args<float>(h_tabf_ + 2 * slot, net, par0, ds);
+        ENG_TRY(hipMemcpyAsync(d_tabf_ + 2 * slot, h_tabf_ + 2 * slot, 2 * sizeof(PassArgs<float>),
+                               hipMemcpyHostToDevice, st));
+    } else {
+        double *gT[3] = {nullptr, nullptr, nullptr};
+        for (int k = 0; k < p->dim; ++k) gT[k] = (double *)(base + L.off_gT) + (size_t)k * n;
+        ENG_TRY(launch_scale<double>(lat, net->gd, (const double *)(base + L.off_dl), gT,
+                                     (double *)(base + L.off_invd), (double *)(base + L.off_vec), (int64_t)(6 * n), st));
+        fill_args<double>(h_tabd_ + 2 * slot, net, par0, ds);
+        ENG_TRY(hipMemcpyAsync(d_tabd_ + 2 * slot, h_tabd_ + 2 * slot, 2 * sizeof(PassArgs<double>),
+                               hipMemcpyHostToDevice, st));
+    }
+    ENG_TRY(hipMemcpyAsync(ds, &init, sizeof(Scalars), hipMemcpyHostToDevice, st));
+    ENG_TRY(hipEventRecord(net->ev_c, st));
+    net->round0 = rounds_;
+    net->kind = kind_of(net);
+    net->first_chunk = chunk_seq_ + 1;
+    net->prev_est = -1.0;
+    net->prev_iters = 0;
+    net->phase = NET_ACTIVE;
+    active_.push_back(net);
+    dirty_ = true;
+    return RN_OK;
+}
+
+int Engine::rebuild(hipStream_t st, std::string *err)
+{
+    int count[kKinds] = {0, 0, 0, 0};
+    for (Net *n : active_) count[n->kind] += n->L.grid;
+    for (int k = 0; k < kKinds; ++k) {
+        if (count[k] > blk_cap_[k]) {
+            const int cap = std::max(count[k], blk_cap_[k] * 3 / 2 + 1024);
+            ENG_TRY(hipStreamSynchronize(st));
+            (void)hipFree(d_blk_[k]);
+            (void)hipHostFree(h_blk_[k]);
+            d_blk_[k] = nullptr;
+            h_blk_[k] = nullptr;
+            ENG_TRY(hipMalloc(&d_blk_[k], sizeof(uint2) * cap));
+            ENG_TRY(hipHostMalloc((void **)&h_blk_[k], sizeof(uint2) * 2 * cap, hipHostMallocDefault));
+            blk_cap_[k] = cap;
+        }
+    }
+    // host staging is double-buffered: the copy queued by the previous rebuild
+    // may not have run yet (one chunk stays in flight)
+    half_ ^= 1;
+    for (int k = 0; k < kKinds; ++k) {
+        nblk_[k] = count[k];
+        if (!count[k]) continue;
+        uint2 *h = h_blk_[k] + (size_t)half_ * blk_cap_[k];
+        int m = 0;
+        for (Net *n : active_)
+            if (n->kind == k)
+                for (int b = 0; b < n->L.grid; ++b) h[m++] = make_uint2((unsigned)n->slot, (unsigned)b);
+        ENG_TRY(hipMemcpyAsync(d_blk_[k], h, sizeof(uint2) * m, hipMemcpyHostToDevice, st));
+    }
+    dirty_ = false;
+    return RN_OK;
+}
+
+int Engine::launch_chunk(int rounds, hipStream_t st, std::string *err)
+{
+    if (active_.empty()) return RN_OK;
+    if (dirty_) {
+        int r = rebuild(st, err);
+        if (r) return r;
+    }
+    peak_active_ = std::max(peak_active_, (int)active_.size());
+    for (int i = 0; i < rounds; ++i) {
+        const int par = (int)(rounds_ & 1);
+        for (int k = 0; k < kKinds; ++k) {
+            if (!nblk_[k]) continue;
+            const int dim = (k & 1) ? 3 : 2;
+            if (k < 2) ENG_TRY(launch_pass<float>(dim, d_tabf_, d_blk_[k], d_scal_, nblk_[k], par, st));
+            else ENG_TRY(launch_pass<double>(dim, d_tabd_, d_blk_[k], d_scal_, nblk_[k], par, st));
+            ++launches_;
+        }
+        ++rounds_;
+    }
+    int hi = 0;
+    for (Net *n : active_) hi = std::max(hi, n->slot + 1);
+    const int b = next_mirror_;
+    ENG_TRY(hipMemcpyAsync(h_scal_[b], d_scal_, sizeof(Scalars) * hi, hipMemcpyDeviceToHost, st));
+    ENG_TRY(hipEventRecord(ev_chunk_[b], st));
+    mirror_hi_[b] = hi;
+    mirror_seq_[b] = ++chunk_seq_;
+    mirror_rounds_[b] = rounds;
+    outstanding_.push_back(b);
+    next_mirror_ ^= 1;
+    return RN_OK;
+}
+
+int Engine::collect(std::vector<Net *> *finished, bool all, hipStream_t st, std::string *err)
+{
+    while (!outstanding_.empty() && (all || outstanding_.size() >= 2)) {
+        const int b = outstanding_.front();
+        outstanding_.pop_front();
+        ENG_TRY(hipEventSynchronize(ev_chunk_[b]));
+        const int in_flight = outstanding_.empty() ? 0 : mirror_rounds_[outstanding_.front()];
+        double min_remain = 1e30;
+        std::vector<Net *> keep;
+        keep.reserve(active_.size());
+        for (Net *n : active_) {
+            if (n->first_chunk > mirror_seq_[b] || n->slot >= mirror_hi_[b]) {
+                keep.push_back(n);
+                continue;
+            }
+            const Scalars &h = h_scal_[b][n->slot];
+            if (h.mode == MODE_DONE) {
+                int r = finalize(n, h, st, err);
+                if (r) return r;
+                if (finished) finished->push_back(n);
+                dirty_ = true;
+                continue;
+            }
+            keep.push_back(n);
+            // remaining iterations from the observed convergence rate
+            if (n->prev_est > 0.0 && h.est_rel > 0.0 && h.est_rel < n->prev_est && h.iters > n->prev_iters) {
+                const double rate = std::log(n->prev_est / h.est_rel) / (double)(h.iters - n->prev_iters);
+                const double remain = std::log(std::max(h.est_rel / h.tol, 1.0)) / rate;
+                min_remain = std::min(min_remain, remain);
+            }
+            n->prev_est = h.est_rel;
+            n->prev_iters = h.iters;
+        }
+        active_.swap(keep);
+        int next = std::min(chunk_ * 2, 256);
+        if (min_remain < 1e29) next = (int)std::min(256.0, std::max(8.0, 0.9 * min_remain - in_flight));
+        chunk_ = active_.empty() ? 16 : next;
+    }
+    return RN_OK;
+}
+
+void Engine::abort_all()
+{
+    active_.clear();
+    outstanding_.clear();
+    free_slots_.clear();
+    for (int s = kSlots - 1; s >= 0; --s) free_slots_.push_back(s);
+    for (auto &b : by_slot_) b = nullptr;
+    dirty_ = true;
+    chunk_ = 16;
+}
+
+int Engine::finalize(Net *net, const Scalars &h, hipStream_t st, std::string *err)
+{
+    const rn_problem *p = &net->prob;
+    const Layout &L = net->L;
+    char *base = net->base;
+    const size_t n = (size_t)L.n;
+    rn_result &r = net->res;
+    r.status = h.status;
+    r.converged = h.converged;
+    r.Q_in = h.Q_in;
+    r.Q_out = h.Q_out;
+    r.G = h.Q_in - h.xr;
+    r.K = r.G * (double)(net->na - 1) / cross_section(p);
+    r.rel_resid = h.rel_resid;
+    r.iters = h.iters;
+    r.refreshes = h.refreshes;
+    r.n_live = net->n_live;
+    r.passes = rounds_ - net->round0;
+    if (r.status == 0 && !r.converged) r.status = RN_ENOCONV;
+    net->status = r.status;
+    const double *P_final = (const double *)(base + L.off_P) + (size_t)(h.refreshes & 1) * n;
+    const hipMemcpyKind kd = p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    ENG_TRY(hipEventRecord(net->ev_d, st));
+    if (p->p_out) ENG_TRY(hipMemcpyAsync(p->p_out, P_final, 8 * n, kd, st));
+    if (p->mask_out) ENG_TRY(hipMemcpyAsync(p->mask_out, base + L.off_mask, n, kd, st));
+    ENG_TRY(hipEventRecord(net->ev, st));
+    by_slot_[net->slot] = nullptr;
+    free_slots_.push_back(net->slot);
+    net->slot = -1;
+    net->phase = NET_FINISHING;
+    return RN_OK;
+}
+
+}  // namespace rn

@@ -156,7 +156,7 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
 
 // Per-workgroup partials, then the last workgroup to arrive reduces them in
 // block order (deterministic) and runs the scalar update.
-__device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, int grid, int mode)
+__device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, int lb, int grid, int mode)
 {
     __shared__ double red[kBlock / kWave][kRed];
     __shared__ int is_last;
@@ -171,7 +171,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, i
         for (int k = 0; k < kRed; ++k) {
             double v = 0.0;
             for (int ww = 0; ww < kBlock / kWave; ++ww) v += red[ww][k];
-            st_through(&partials[(size_t)blockIdx.x * kRed + k], v);
+            st_through(&partials[(size_t)lb * kRed + k], v);
         }
         // wait until this thread's write-through stores have completed
         // (s_waitcnt with every counter at 0), then take a ticket
@@ -379,15 +379,24 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     }
 }
 
+// One launch runs one pass of every network listed in the block table: entry
+// blk[b] = (network, block index within that network's grid). Each network
+// has its own arguments (two parities of the double-buffered state), partial
+// sums, ticket and control block, so networks advance independently and a
+// network's arithmetic does not depend on what else is in the launch.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void pass2d_kernel(PassArgs<T> a)
+__global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__restrict__ tab,
+                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity)
 {
-    Scalars *s = a.s;
+    const uint2 e = blk[blockIdx.x];
+    const PassArgs<T> &a = tab[2 * e.x + parity];
+    const int lb = (int)e.y;
+    Scalars *s = scal + e.x;          // == a.s; indexed directly to shorten the load chain
     const int mode = s->mode;
     if (mode == MODE_DONE) return;
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int tile = xcd_remap(blockIdx.x, a.grid) * (kBlock / kWave) + w;
+    const int tile = xcd_remap(lb, a.grid) * (kBlock / kWave) + w;
     const int m = (int)(s->refreshes & 1);
     const double sa = s->sigma * s->alpha;
     if (tile < a.ntiles) {
@@ -403,7 +412,7 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(PassArgs<T> a)
                 refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
         }
     }
-    finish_pass(acc, a.partials, s, a.grid, mode);
+    finish_pass(acc, a.partials, s, lb, a.grid, mode);
 }
 
 // ---------------------------------------------------------------- 3D pass
@@ -523,13 +532,17 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void pass3d_kernel(PassArgs<T> a)
+__global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__restrict__ tab,
+                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity)
 {
-    Scalars *s = a.s;
+    const uint2 e = blk[blockIdx.x];
+    const PassArgs<T> &a = tab[2 * e.x + parity];
+    const int lb = (int)e.y;
+    Scalars *s = scal + e.x;          // == a.s; indexed directly to shorten the load chain
     const int mode = s->mode;
     if (mode == MODE_DONE) return;
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    const int tile = xcd_remap(blockIdx.x, a.grid);
+    const int tile = xcd_remap(lb, a.grid);
     const int m = (int)(s->refreshes & 1);
     const double sa = s->sigma * s->alpha;
     // tile index is uniform per workgroup: idle workgroups still reach the reduction
@@ -554,7 +567,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(PassArgs<T> a)
                 }
         }
     }
-    finish_pass(acc, a.partials, s, a.grid, mode);
+    finish_pass(acc, a.partials, s, lb, a.grid, mode);
 }
 
 // ---------------------------------------------------------------- setup kernels
@@ -815,10 +828,12 @@ hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipSt
 }
 
 template <typename T>
-hipError_t launch_pass(int dim, const PassArgs<T> &a, hipStream_t st)
+hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
+                       hipStream_t st)
 {
-    if (dim == 2) pass2d_kernel<T><<<a.grid, kBlock, 0, st>>>(a);
-    else pass3d_kernel<T><<<a.grid, kBlock, 0, st>>>(a);
+    if (nblocks <= 0) return hipSuccess;
+    if (dim == 2) pass2d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
+    else pass3d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
     return hipGetLastError();
 }
 
@@ -826,7 +841,9 @@ template hipError_t launch_scale<float>(const Lat &, const double *const[3], con
                                         float *, float *, int64_t, hipStream_t);
 template hipError_t launch_scale<double>(const Lat &, const double *const[3], const double *, double *const[3],
                                          double *, double *, int64_t, hipStream_t);
-template hipError_t launch_pass<float>(int, const PassArgs<float> &, hipStream_t);
-template hipError_t launch_pass<double>(int, const PassArgs<double> &, hipStream_t);
+template hipError_t launch_pass<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int,
+                                       hipStream_t);
+template hipError_t launch_pass<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int,
+                                        hipStream_t);
 
 }  // namespace rn

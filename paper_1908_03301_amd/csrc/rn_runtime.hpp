@@ -1,0 +1,174 @@
+// rn_runtime.hpp -- host runtime of librn: device memory pool, per-network
+// solve state and the multi-network iteration engine shared by rn_solve,
+// rn_solve_batch and the request server.
+#pragma once
+
+#include "../../include/rn.h"
+#include "rn_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace rn {
+
+// ------------------------------------------------------------------ memory pool
+// Device memory in slabs (hipMalloc'd on demand, released with the context),
+// carved first-fit. The sum of slab sizes never exceeds the context budget.
+class Pool {
+public:
+    explicit Pool(size_t budget = 0) : budget_(budget) {}
+    ~Pool();
+    void set_budget(size_t b) { budget_ = b; }
+    size_t budget() const { return budget_; }
+    size_t in_use() const { return in_use_; }
+    // nullptr with *err = hipSuccess when the request does not fit the budget now
+    void *alloc(size_t bytes, hipError_t *err);
+    void free(void *p);
+    void release_all();
+
+private:
+    struct Slab {
+        char *base;
+        size_t size;
+        std::map<size_t, size_t> free_;   // offset -> length
+        std::map<size_t, size_t> used_;   // offset -> length
+    };
+    std::vector<Slab> slabs_;
+    size_t budget_ = 0, reserved_ = 0, in_use_ = 0;
+};
+
+// ------------------------------------------------------------------ layout
+struct Layout {
+    int64_t n = 0;
+    int dim = 2, s = 8;
+    bool copy_g = false;
+    int grid = 8, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_z = 16;
+    size_t off_g64 = 0, off_P = 0, off_dl = 0, off_mask = 0, off_gT = 0, off_invd = 0, off_vec = 0,
+           off_part = 0, off_cnt = 0, total = 0;
+};
+Layout make_layout(const rn_problem *p, const rn_opts *o);
+
+// ------------------------------------------------------------------ one network
+enum NetPhase { NET_NEW, NET_PREPARING, NET_ACTIVE, NET_FINISHING, NET_DONE };
+
+struct Net {
+    rn_problem prob{};
+    rn_opts opts{};
+    Layout L;
+    char *base = nullptr;           // device arena (pool)
+    const double *gd[3] = {nullptr, nullptr, nullptr};
+    int slot = -1;                  // control block / descriptor slot in the engine
+    int kind = 0;                   // 2D/3D x FP32/FP64, see Engine::kind_of
+    NetPhase phase = NET_NEW;
+    int64_t n_live = 0;
+    int64_t na = 0;                 // extent along the flow axis
+    hipEvent_t ev = nullptr;        // end of the last enqueued phase (setup or outputs)
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;   // setup start / end (timing)
+    hipEvent_t ev_c = nullptr, ev_d = nullptr;   // iteration loop start / end (timing)
+    int64_t round0 = 0;             // engine pass round at activation
+    rn_result res{};
+    int status = RN_OK;
+    double t_start = 0.0;           // host clock at submission
+    uint64_t ticket = 0;
+    double prev_est = -1.0;
+    int64_t prev_iters = 0;
+    int64_t first_chunk = 0;        // first chunk whose status mirror covers this network
+    // host copies (server path: the caller's buffers stay valid until completion)
+};
+
+// ------------------------------------------------------------------ engine
+class Engine {
+public:
+    static constexpr int kSlots = 4096;
+    static constexpr int kKinds = 4;   // (dim 2 | 3) x (fp32 | fp64)
+
+    int init(hipStream_t st, std::string *err);
+    void destroy();
+    bool full() const { return free_slots_.empty(); }
+    // enqueue upload, validation, connectivity and counters of a network
+    int prepare(Net *net, hipStream_t st, std::string *err);
+    // the prepared network's counters are on the host: activate it, or finish it
+    // at once (no live node, invalid values). Returns RN_OK or an error status.
+    int after_prepare(Net *net, hipStream_t st, std::string *err);
+    // launch `rounds` pass rounds of every active network, then queue a read
+    // of every control block into a host mirror
+    int launch_chunk(int rounds, hipStream_t st, std::string *err);
+    // wait for the oldest outstanding mirror (all of them when `all`) while two
+    // are outstanding; finalize the networks it shows finished (outputs
+    // enqueued, ev recorded) and append them to *finished
+    int collect(std::vector<Net *> *finished, bool all, hipStream_t st, std::string *err);
+    int active_count() const { return (int)active_.size(); }
+    int outstanding() const { return (int)outstanding_.size(); }
+    int next_chunk() const { return chunk_; }
+    int64_t launches() const { return launches_; }
+    int64_t chunk_seq() const { return chunk_seq_; }
+    int peak_active() const { return peak_active_; }
+    // forget every network (after a device error): slots, tables, mirrors
+    void abort_all();
+
+private:
+    int kind_of(const Net *n) const { return (n->prob.dim == 3 ? 1 : 0) + (n->L.s == 8 ? 2 : 0); }
+    int rebuild(hipStream_t st, std::string *err);
+    int finalize(Net *net, const Scalars &h, hipStream_t st, std::string *err);
+
+    Scalars *d_scal_ = nullptr, *h_scal_[2] = {nullptr, nullptr}, *h_init_ = nullptr;
+    PassArgs<float> *d_tabf_ = nullptr, *h_tabf_ = nullptr;
+    PassArgs<double> *d_tabd_ = nullptr, *h_tabd_ = nullptr;
+    unsigned long long *h_cnt_ = nullptr;   // [kSlots][4] pinned
+    uint2 *d_blk_[kKinds] = {nullptr, nullptr, nullptr, nullptr};
+    uint2 *h_blk_[kKinds] = {nullptr, nullptr, nullptr, nullptr};
+    int blk_cap_[kKinds] = {0, 0, 0, 0};
+    int nblk_[kKinds] = {0, 0, 0, 0};
+    hipEvent_t ev_chunk_[2] = {nullptr, nullptr};
+    std::deque<int> outstanding_;           // mirrors with a queued status read, oldest first
+    int next_mirror_ = 0, half_ = 0;
+    int mirror_hi_[2] = {0, 0};             // slots copied into each mirror
+    int64_t mirror_seq_[2] = {0, 0};        // chunk number each mirror follows
+    int mirror_rounds_[2] = {0, 0};
+    int64_t chunk_seq_ = 0;
+    std::vector<int> free_slots_;
+    std::vector<Net *> active_;
+    Net *by_slot_[kSlots] = {};
+    bool dirty_ = true;
+    int64_t rounds_ = 0;                    // pass rounds issued (parity of the next round)
+    int64_t launches_ = 0;
+    int chunk_ = 16;
+    int peak_active_ = 0;                   // most networks that shared one launch
+};
+
+}  // namespace rn
+
+// ------------------------------------------------------------------ context
+struct rn_server;
+
+struct rn_ctx {
+    int device = 0;
+    size_t budget = 0;
+    hipStream_t own = nullptr;
+    hipStream_t stream = nullptr;
+    std::string err;
+    rn::Pool pool;
+    rn::Engine engine;
+    bool engine_ok = false;
+    hipEvent_t ev_t[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::mutex call_mu;             // serialises the synchronous entry points with the server
+    std::atomic<int> callers{0};    // threads waiting for call_mu (the server steps aside for them)
+    rn_server *server = nullptr;
+};
+
+namespace rn {
+int check_shape(const rn_problem *p);
+int check_opts(const rn_opts *o);
+bool host_values_ok(const rn_problem *p);
+double cross_section(const rn_problem *p);
+double now_s();
+}  // namespace rn
