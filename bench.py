@@ -37,6 +37,14 @@ WORKLOADS = {
     "strat3d_256": dict(desc="3D 256^3 layered 1D-FBM ln g (H=0.8, sigma=2), occupancy 0.27, K_x and K_z",
                         make=lambda I: I.workload_strat_3d_256(), axes=(0, 2)),
 }
+MULTI = {
+    "batch512": "512 independent networks in one batched launch sequence: 2D side U{64..1024} and 3D side "
+                "U{32..128} (half each), FBM ln g (H~U(0.5,0.9), sigma=1), occupancy U(0.55,1) in 2D and "
+                "U(0.3,1) in 3D, flow along x",
+    "serve": "served request stream, Poisson arrivals at 0.7 x the measured batched saturation rate; nodes "
+             "log-uniform in [1e4, 3e7], 2D/3D 50/50, FBM ln g (H=0.75, sigma=1.5), occupancy U(0.3,1), "
+             "flow along x; requests cycle through a pre-generated seeded pool",
+}
 
 
 def pass_bytes(dim: int, n: int, s: int, live: int) -> dict:
@@ -109,7 +117,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fbm2d_2048", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="fbm2d_2048", choices=sorted(WORKLOADS) + sorted(MULTI))
+    ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
+    ap.add_argument("--pool", type=int, default=24, help="serve: distinct networks generated for the stream")
+    ap.add_argument("--batch-size", type=int, default=512, help="batch512: networks in the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -140,6 +151,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": nbytes}), flush=True)
+        return
+
+    if args.workload in MULTI:
+        out = batch_bench(args, B, I, np) if args.workload == "batch512" else serve_bench(args, B, I, np)
+        print(json.dumps(out), flush=True)
         return
 
     wl = dict(WORKLOADS[args.workload])
@@ -214,6 +230,180 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(net, wl, args, res_d if not args.no_fp64 else None)
     print(json.dumps(out), flush=True)
+
+
+def _gen_batch(spec):
+    from paper_1908_03301_amd import inputs as I
+    return I.batch_network(spec)
+
+
+def _gen_stream(req):
+    from paper_1908_03301_amd import inputs as I
+    return I.stream_network(req)
+
+
+def generate(fn, items, label):
+    """Seeded networks generated in a process pool (same bytes as serial generation)."""
+    from concurrent.futures import ProcessPoolExecutor
+    out = [None] * len(items)
+    t0 = time.time()
+    workers = max(1, min(8, len(os.sched_getaffinity(0)) - 1))
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for k, net in enumerate(ex.map(fn, items, chunksize=4)):
+            out[k] = net
+            if (k + 1) % 32 == 0 or k + 1 == len(items):
+                print(f"[bench] {label}: generated {k + 1}/{len(items)} networks in {time.time() - t0:.1f}s",
+                      file=sys.stderr, flush=True)
+    return out
+
+
+def _contract(args, value, unit, total_s, steps, config, dtype="fp32+fp64"):
+    return {"metric": METRIC, "value": round(value, 4), "unit": unit, "n_gpus": 1, "steps": steps,
+            "warmup": args.warmup, "ms_per_step": round(1e3 * total_s / max(steps, 1), 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def _net_bytes(r, dim, n, s):
+    pb = pass_bytes(dim, n, s, r.n_live)
+    return r.iters * pb["cg"] + r.refreshes * pb["refresh"]
+
+
+def batch_bench(args, B, I, np):
+    """512 uneven networks solved together (rn_solve_batch), mixed precision to tol.
+
+    Compared with the same batch in FP64, and with plain FP64 CG run one
+    network at a time (rn_solve per network, in order).
+    """
+    import torch
+    specs = I.batch_specs(args.batch_size)
+    nets = generate(_gen_batch, specs, "batch")
+    gd = [[torch.from_numpy(a).to("cuda") for a in n.g] for n in nets]
+    torch.cuda.synchronize()
+    probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=0, g=g) for n, g in zip(nets, gd)]
+    ctx = B.Context(0)
+
+    def run(prec, steps):
+        walls, res = [], None
+        for it in range(args.warmup + steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = ctx.solve_batch(probs, B.opts(prec, args.tol))
+            w = time.perf_counter() - t
+            bad = [r.status for r in res if r.status != 0]
+            print(f"[bench] batch prec={prec} {'warmup' if it < args.warmup else 'step'} {it}: {w:.3f}s "
+                  f"failed={len(bad)}", file=sys.stderr, flush=True)
+            if bad:
+                raise SystemExit(f"batch members failed: {bad[:5]}")
+            if it >= args.warmup:
+                walls.append(w)
+        return walls, res
+
+    walls_m, res_m = run(B.RN_MIXED, args.steps)
+    tot_m = sum(walls_m)
+    value = len(probs) * len(walls_m) / tot_m
+    bytes_m = sum(_net_bytes(r, n.dim, n.n, 4) for r, n in zip(res_m, nets))
+    out = _contract(args, value, "solves/s", tot_m, len(walls_m),
+                    {"workload": MULTI["batch512"], "networks": len(probs), "nodes": sum(n.n for n in nets),
+                     "tol": args.tol, "precision": "fp32 inner CG + fp64 refresh/solution/flux",
+                     "inputs": "resident in HBM"})
+    out["batch_wall_s"] = round(min(walls_m), 3)
+    out["roofline"] = {"bound": "hbm", "achieved": round(bytes_m / min(walls_m) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(bytes_m / min(walls_m) / 1e9 / HBM_PEAK_GBS, 4),
+                       "traffic": None, "kernel": "pass2d/pass3d_kernel<float> (all networks per launch)",
+                       "note": "algorithmic bytes of every member's passes / batch wall time"}
+    walls_d, res_d = run(B.RN_FP64, 1)
+    out["fp64_batched_solves_per_s"] = round(len(probs) / min(walls_d), 4)
+    # plain FP64 CG, one network at a time
+    t = time.perf_counter()
+    for pr in probs:
+        r = ctx.solve(pr, B.opts(B.RN_FP64, args.tol))
+        if r.status != 0:
+            raise SystemExit(f"fp64 solve failed: {r.as_dict()}")
+    w = time.perf_counter() - t
+    out["fp64_cg_one_at_a_time_solves_per_s"] = round(len(probs) / w, 4)
+    out["mixed_batched_vs_fp64_one_at_a_time"] = round(value / out["fp64_cg_one_at_a_time_solves_per_s"], 3)
+    out["max_K_rel_diff_mixed_vs_fp64"] = float(max(abs(a.K / b.K - 1.0) for a, b in zip(res_m, res_d) if b.K > 0))
+    ctx.close()
+    return out
+
+
+def serve_bench(args, B, I, np):
+    """Served stream (rn_submit / rn_poll) vs plain FP64 CG served first-in first-out.
+
+    Requests cycle through a pool of pre-generated networks (device resident).
+    The mixed server's saturation rate is measured first with all requests
+    submitted at once; the stream then arrives as a Poisson process at 0.7
+    times that rate. The same arrival times are replayed against plain FP64
+    CG solving one request at a time in arrival order.
+    """
+    import torch
+    reqs = I.stream_requests(args.pool, rate_per_s=1.0)
+    pool = generate(_gen_stream, reqs, "stream pool")
+    gd = [[torch.from_numpy(a).to("cuda") for a in n.g] for n in pool]
+    torch.cuda.synchronize()
+    probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=0, g=g) for n, g in zip(pool, gd)]
+    om, od = B.opts(B.RN_MIXED, args.tol), B.opts(B.RN_FP64, args.tol)
+    nreq = args.requests
+    order = [i % len(pool) for i in range(nreq)]
+
+    def serve(arrivals, c):
+        lat, submitted, done = [None] * nreq, {}, 0
+        tstart = time.perf_counter()
+        i = 0
+        while done < nreq:
+            now = time.perf_counter() - tstart
+            while i < nreq and arrivals[i] <= now:
+                submitted[c.submit(probs[order[i]], om)] = (i, tstart + arrivals[i])
+                i += 1
+            for t in list(submitted):
+                st, r = c.poll(t)
+                if st == B.RN_EAGAIN:
+                    continue
+                k, ta = submitted.pop(t)
+                if st != 0:
+                    raise SystemExit(f"served request failed: {st}")
+                lat[k] = time.perf_counter() - ta
+                done += 1
+            time.sleep(0.0002)
+        return lat, time.perf_counter() - tstart
+
+    # saturation: everything submitted at t = 0
+    c = B.Context(0)
+    _, make = serve([0.0] * nreq, c)
+    sat = nreq / make
+    c.close()
+    rate = 0.7 * sat
+    rng = I.rng_for(50_000_000)
+    arrivals = list(np.cumsum(rng.exponential(1.0 / rate, nreq)))
+    c = B.Context(0)
+    lat, make = serve(arrivals, c)
+    c.close()
+    # plain FP64 CG, first in first out, same arrivals
+    ctx = B.Context(0)
+    lat_d, tfree = [], 0.0
+    tstart = time.perf_counter()
+    for k in range(nreq):
+        now = time.perf_counter() - tstart
+        if arrivals[k] > now:
+            time.sleep(arrivals[k] - now)
+        r = ctx.solve(probs[order[k]], od)
+        if r.status != 0:
+            raise SystemExit(f"fp64 request failed: {r.as_dict()}")
+        lat_d.append(time.perf_counter() - tstart - arrivals[k])
+    make_d = time.perf_counter() - tstart
+    ctx.close()
+    value = nreq / make
+    out = _contract(args, value, "solves/s", make, nreq,
+                    {"workload": MULTI["serve"], "requests": nreq, "pool": len(pool), "rate_per_s": round(rate, 3),
+                     "saturation_solves_per_s": round(sat, 3), "tol": args.tol,
+                     "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"})
+    out["latency_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 2),
+                         "p99": round(1e3 * float(np.percentile(lat, 99)), 2)}
+    out["fp64_cg_fifo"] = {"solves_per_s": round(nreq / make_d, 3),
+                           "p50_ms": round(1e3 * float(np.percentile(lat_d, 50)), 2),
+                           "p99_ms": round(1e3 * float(np.percentile(lat_d, 99)), 2)}
+    return out
 
 
 def cpu_baseline(net, wl, args, res_fp64):
