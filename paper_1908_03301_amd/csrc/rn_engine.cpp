@@ -11,6 +11,7 @@
 #include "rn_runtime.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -495,6 +496,7 @@ int Engine::collect(std::vector<Net *> *finished, bool all, hipStream_t st, std:
         ENG_TRY(hipEventSynchronize(ev_chunk_[b]));
         const int in_flight = outstanding_.empty() ? 0 : mirror_rounds_[outstanding_.front()];
         double min_remain = 1e30;
+        int64_t min_iters = INT64_MAX;
         std::vector<Net *> keep;
         keep.reserve(active_.size());
         for (Net *n : active_) {
@@ -519,10 +521,16 @@ int Engine::collect(std::vector<Net *> *finished, bool all, hipStream_t st, std:
             }
             n->prev_est = h.est_rel;
             n->prev_iters = h.iters;
+            min_iters = std::min(min_iters, h.iters);
         }
         active_.swap(keep);
+        // next chunk: the predicted remaining iterations of the closest network,
+        // less what is already in flight; rounds issued after a network
+        // converges are idle, so the chunk also stays below a quarter of the
+        // iterations done so far (a bound on the overshoot of fast solves)
         int next = std::min(chunk_ * 2, 256);
         if (min_remain < 1e29) next = (int)std::min(256.0, std::max(8.0, 0.9 * min_remain - in_flight));
+        if (min_iters != INT64_MAX) next = (int)std::min<int64_t>(next, std::max<int64_t>(16, min_iters / 4));
         chunk_ = active_.empty() ? 16 : next;
     }
     return RN_OK;

@@ -416,10 +416,32 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
 }
 
 // ---------------------------------------------------------------- 3D pass
-// A workgroup owns a 64 (x) x 16 (y) x tile_z (z) block; each wave covers 4
-// rows. It streams up z: the p' plane (with a one-node halo ring) is staged in
-// a triple-buffered LDS tile, p' of planes z-1, z, z+1 stays in registers.
+// A workgroup owns a 64 (x) x 16 (y) x tile_z (z) block; wave w covers rows
+// 4w..4w+3 of the 16, one node per lane per row. It streams up z with a
+// software pipeline: in the iteration that applies the stencil on plane z it
+// turns the already loaded plane z+1 into p' (registers, and the LDS tile with
+// its halo ring when z+1 is inside the block) and issues the loads of plane
+// z+2 and of the bonds of plane z+1, so each plane's memory traffic is in
+// flight while the previous plane is computed. The p' plane tile is
+// triple-buffered in LDS (one barrier per plane). Loads use clamped in-bounds
+// addresses and no branch on loaded data; off-lattice values are zeroed by
+// selects. Bonds to the -x, -y, -z neighbours come from a shuffle, the row
+// above in the same thread, and the previous plane.
 constexpr int kRows = kTY / (kBlock / kWave);
+
+template <typename T>
+struct Raw3 {                  // one plane's loads for this thread
+    T d[kRows], r[kRows], q[kRows], p[kRows];
+    double P[kRows];
+    T hd, hr, hq, hp;          // halo-ring node of this thread (if any)
+};
+
+template <typename T>
+struct Bond3 {                 // bonds of one plane for this thread's rows
+    T x[kRows], y[kRows], z[kRows];
+    T xh;                      // lanes 0..kRows-1: bond (x0-1) -> x0 of row `lane`
+    T yh;                      // bond from the row above this wave's first row
+};
 
 template <typename T>
 __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int y0, int z0,
@@ -430,6 +452,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int x = x0 + lane;
+    const bool xok = x < nx;
+    const int xc = xok ? x : nx - 1;
     const T *__restrict__ rs = a.src.r;
     const T *__restrict__ qs = a.src.q;
     const T *__restrict__ ps = a.src.p;
@@ -440,94 +464,162 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
     const T *__restrict__ gz = a.gT[2];
-
-    auto pnew = [&](int xx, int yy, int zz) -> T {
-        if (xx < 0 || xx >= nx || yy < 0 || yy >= ny || zz < 0 || zz >= nz) return T(0);
-        const int64_t i = xx + sy * yy + sz * zz;
-        const T d = dv[i];
-        return d * (rs[i] - alpha * qs[i]) + beta * ps[i];
-    };
-
-    T pz[3][kRows];          // p' of planes zz-2, zz-1, zz (ring indexed by plane % 3)
-    T rz[2][kRows];          // r' of planes zz-1, zz (ring by plane % 2)
-    T dz[2][kRows];          // 1/d of planes zz-1, zz
+    const int yw = y0 + w * kRows;                 // first row of this wave
+    bool rok[kRows];
+    int64_t rowoff[kRows];                         // clamped x + sy * y of each row
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
-        pz[0][j] = pz[1][j] = pz[2][j] = T(0);
-        rz[0][j] = rz[1][j] = T(0);
-        dz[0][j] = dz[1][j] = T(0);
+        const int yy = yw + j;
+        rok[j] = xok && yy < ny;
+        rowoff[j] = xc + sy * (yy < ny ? yy : ny - 1);
     }
+    // halo ring: wave 0 row y0-1, wave 1 row y0+16, wave 2 lanes 0..15 column
+    // x0-1 and lanes 16..31 column x0+64 (rows y0..y0+15)
+    int hx, hy, hrow, hcol;
+    if (w == 0) { hx = x; hy = y0 - 1; hrow = 0; hcol = 1 + lane; }
+    else if (w == 1) { hx = x; hy = y0 + kTY; hrow = kTY + 1; hcol = 1 + lane; }
+    else if (w == 2 && lane < kTY) { hx = x0 - 1; hy = y0 + lane; hrow = 1 + lane; hcol = 0; }
+    else if (w == 2 && lane < 2 * kTY) { hx = x0 + kTX; hy = y0 + lane - kTY; hrow = 1 + lane - kTY; hcol = kTX + 1; }
+    else { hx = -1; hy = -1; hrow = -1; hcol = 0; }
+    const bool hok = hx >= 0 && hx < nx && hy >= 0 && hy < ny;
+    const int64_t hoff = hok ? hx + sy * hy : 0;
+    // bond halos: lane j < kRows holds gx at (x0-1, yw+j); every lane holds gy at (x, yw-1)
+    const bool xhok = lane < kRows && x0 >= 1 && yw + lane < ny;
+    const int64_t xhoff = xhok ? (x0 - 1) + sy * (yw + lane) : 0;
+    const bool yhok = xok && yw >= 1 && yw - 1 < ny;
+    const int64_t yhoff = yhok ? xc + sy * (yw - 1) : 0;
 
-    for (int zz = z0 - 1; zz <= z1; ++zz) {
-        const int b = (zz + 3) % 3;          // zz >= -1
-        const int h = (zz + 2) & 1;
-        const bool inner = zz >= z0 && zz < z1;
-        // ---- stage plane zz: own rows
+    auto zc_ = [&](int zz) { return (int64_t)(zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz)) * sz; };
+    auto load_raw = [&](Raw3<T> &R, int zz, bool ring) {
+        const int64_t zo = zc_(zz);
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
-            const int yy = y0 + w * kRows + j;
-            T pv = T(0), rv = T(0), dvi = T(0);
-            if (x < nx && yy < ny && zz >= 0 && zz < nz) {
-                const int64_t i = x + sy * yy + sz * zz;
-                dvi = dv[i];
-                const T pold = ps[i];
-                rv = rs[i] - alpha * qs[i];
-                pv = dvi * rv + beta * pold;
-                if (inner) {
-                    P[i] += sa * (double)pold;
-                    rd[i] = rv;
-                }
-            }
-            pz[b][j] = pv;
-            rz[h][j] = rv;
-            dz[h][j] = dvi;
-            lp[b][1 + w * kRows + j][1 + lane] = pv;
+            const int64_t i = rowoff[j] + zo;
+            R.d[j] = dv[i];
+            R.r[j] = rs[i];
+            R.q[j] = qs[i];
+            R.p[j] = ps[i];
+            R.P[j] = P[i];
         }
-        // ---- halo ring of plane zz
-        if (w == 0) {
-            lp[b][0][1 + lane] = pnew(x, y0 - 1, zz);
-        } else if (w == 1) {
-            lp[b][kTY + 1][1 + lane] = pnew(x, y0 + kTY, zz);
-        } else if (w == 2) {
-            if (lane < kTY) lp[b][1 + lane][0] = pnew(x0 - 1, y0 + lane, zz);
-            else if (lane < 2 * kTY) lp[b][1 + lane - kTY][kTX + 1] = pnew(x0 + kTX, y0 + lane - kTY, zz);
+        if (ring) {
+            const int64_t i = hoff + zo;
+            R.hd = dv[i];
+            R.hr = rs[i];
+            R.hq = qs[i];
+            R.hp = ps[i];
         }
-        __syncthreads();
-        // ---- stencil on plane zc = zz - 1
-        const int zc = zz - 1;
-        if (zc >= z0 && zc < z1) {
-            const int bc = (zc + 3) % 3, bm = (zc + 2) % 3, hc = (zc + 2) & 1;
+    };
+    auto load_bonds = [&](Bond3<T> &G, int zz) {
+        const int64_t zo = zc_(zz);
 #pragma unroll
-            for (int j = 0; j < kRows; ++j) {
-                const int ly = 1 + w * kRows + j;
-                const int yy = y0 + w * kRows + j;
-                const T pc = pz[bc][j];
-                const T dc = dz[hc][j];
-                T qv = T(0);
-                if (x < nx && yy < ny) {
-                    const int64_t i = x + sy * yy + sz * zc;
-                    const T gxc = gx[i];
-                    const T gxl = x >= 1 ? gx[i - 1] : T(0);
-                    const T gyc = gy[i];
-                    const T gyl = yy >= 1 ? gy[i - sy] : T(0);
-                    const T gzc = gz[i];
-                    const T gzl = zc >= 1 ? gz[i - sz] : T(0);
-                    qv = gxl * (pc - lp[bc][ly][lane]) + gxc * (pc - lp[bc][ly][lane + 2]) +
-                         gyl * (pc - lp[bc][ly - 1][1 + lane]) + gyc * (pc - lp[bc][ly + 1][1 + lane]) +
-                         gzl * (pc - pz[bm][j]) + gzc * (pc - pz[b][j]);
-                    if (dc == T(0)) qv = T(0);
-                    pd[i] = pc;
-                    qd[i] = qv;
-                }
-                const double dp = (double)pc, dq = (double)qv, dr = (double)rz[hc][j];
-                const double dd = (double)dc, dzv = dd * dr;
-                acc[0] += dp * dq;
-                acc[1] += dzv * dq;
-                acc[2] += dq * dq * dd;
-                acc[3] += dr * dzv;
-                acc[4] += dr * dr;
-            }
+        for (int j = 0; j < kRows; ++j) {
+            const int64_t i = rowoff[j] + zo;
+            G.x[j] = gx[i];
+            G.y[j] = gy[i];
+            G.z[j] = gz[i];
         }
+        const T xh = gx[xhoff + zo], yh = gy[yhoff + zo];
+        G.xh = xhok ? xh : T(0);           // no bond left of x = 0
+        G.yh = yhok ? yh : T(0);           // no bond below y = 0
+    };
+    auto pprime = [&](T d, T r, T q, T p) { return d * (r - alpha * q) + beta * p; };
+
+    T pm[kRows], pc[kRows], pn[kRows];   // p' of planes zc-1, zc, zc+1 (own rows)
+    T rc[kRows], dc[kRows];              // r' and 1/d of plane zc
+    T rn[kRows], dn[kRows];              // r' and 1/d of plane zc+1
+    T gzm[kRows];                        // gz of the bond (zc-1) -> zc
+    Raw3<T> R;
+    Bond3<T> Gc, Gn;
+
+    // ---- prologue: plane z0-1 (own rows), plane z0 (rows, ring, LDS), bonds of z0
+    {
+        const bool in = z0 - 1 >= 0;
+        load_raw(R, z0 - 1, false);
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) pm[j] = (in && rok[j]) ? pprime(R.d[j], R.r[j], R.q[j], R.p[j]) : T(0);
+        load_raw(R, z0, true);
+        load_bonds(Gc, z0);
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) gzm[j] = (in && rok[j]) ? gz[rowoff[j] + zc_(z0 - 1)] : T(0);
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            const bool ok = rok[j];
+            const T r_ = R.r[j] - alpha * R.q[j];
+            pc[j] = ok ? R.d[j] * r_ + beta * R.p[j] : T(0);
+            rc[j] = ok ? r_ : T(0);
+            dc[j] = ok ? R.d[j] : T(0);
+            if (ok) {
+                const int64_t i = rowoff[j] + (int64_t)z0 * sz;
+                P[i] = R.P[j] + sa * (double)R.p[j];
+                rd[i] = r_;
+            }
+            lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
+        }
+        if (hrow >= 0) lp[z0 % 3][hrow][hcol] = hok ? pprime(R.hd, R.hr, R.hq, R.hp) : T(0);
+        load_raw(R, z0 + 1, z0 + 1 < z1);
+    }
+
+    for (int zc = z0; zc < z1; ++zc) {
+        const int zn = zc + 1;
+        const bool nin = zn < z1;                // plane zc+1 belongs to this block
+        const bool nlat = zn < nz;               // plane zc+1 is inside the lattice
+        // (a) plane zc+1 from the loads issued one iteration ago
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            const bool ok = rok[j] && nlat;
+            const T r_ = R.r[j] - alpha * R.q[j];
+            pn[j] = ok ? R.d[j] * r_ + beta * R.p[j] : T(0);
+            rn[j] = ok ? r_ : T(0);
+            dn[j] = ok ? R.d[j] : T(0);
+            if (ok && nin) {
+                const int64_t i = rowoff[j] + (int64_t)zn * sz;
+                P[i] = R.P[j] + sa * (double)R.p[j];
+                rd[i] = r_;
+            }
+            if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];
+        }
+        if (nin && hrow >= 0) lp[zn % 3][hrow][hcol] = hok ? pprime(R.hd, R.hr, R.hq, R.hp) : T(0);
+        // (b) loads for the next iteration
+        if (zn + 1 <= z1) load_raw(R, zn + 1, zn + 1 < z1);
+        if (nin) load_bonds(Gn, zn);
+        __syncthreads();
+        // (c) stencil on plane zc
+        const int b = zc % 3;
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            const int ly = 1 + w * kRows + j;
+            T gxl = __shfl_up(Gc.x[j], 1, kWave);
+            const T gxh = __shfl(Gc.xh, j, kWave);
+            if (lane == 0) gxl = gxh;
+            const T gyl = j == 0 ? Gc.yh : Gc.y[j - 1];
+            const T p0 = pc[j];
+            T qv = gxl * (p0 - lp[b][ly][lane]) + Gc.x[j] * (p0 - lp[b][ly][lane + 2]) +
+                   gyl * (p0 - lp[b][ly - 1][1 + lane]) + Gc.y[j] * (p0 - lp[b][ly + 1][1 + lane]) +
+                   gzm[j] * (p0 - pm[j]) + Gc.z[j] * (p0 - pn[j]);
+            if (dc[j] == T(0)) qv = T(0);
+            if (rok[j]) {
+                const int64_t i = rowoff[j] + (int64_t)zc * sz;
+                pd[i] = p0;
+                qd[i] = qv;
+            }
+            const double dp = (double)p0, dq = (double)qv, dr = (double)rc[j];
+            const double dd = (double)dc[j], dzv = dd * dr;
+            acc[0] += dp * dq;
+            acc[1] += dzv * dq;
+            acc[2] += dq * dq * dd;
+            acc[3] += dr * dzv;
+            acc[4] += dr * dr;
+        }
+        // rotate
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) {
+            gzm[j] = rok[j] ? Gc.z[j] : T(0);
+            pm[j] = pc[j];
+            pc[j] = pn[j];
+            rc[j] = rn[j];
+            dc[j] = dn[j];
+        }
+        if (nin) Gc = Gn;
     }
 }
 
