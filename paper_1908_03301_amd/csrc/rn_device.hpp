@@ -70,7 +70,7 @@ struct PassArgs {
     int nx, ny, nz, axis;
     int ntx, nty, ntz;           // tile counts
     int tile_y, tile_z;          // rows per 2D strip / planes per 3D tile
-    int ntiles;                  // total tiles (2D: wave strips; 3D: workgroup tiles)
+    int ntiles;                  // total workgroup tiles
     int grid;                    // workgroups of this network per pass (multiple of 8)
     // FP64 data
     const double *g64[3];        // original conductances
@@ -105,8 +105,9 @@ template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
                        hipStream_t st);
 
-// tile geometry of the pass kernels: 2D tiles are 64 x kTY2f (FP32) or
-// 64 x kTY2d (FP64) per wave, 3D tiles 64 x kTY x tile_z per workgroup
+// tile geometry of the pass kernels: a 2D workgroup tile is 64 x 4 kTY2f
+// (FP32) or 64 x 4 kTY2d (FP64), kTY2f or kTY2d rows per wave; a 3D workgroup
+// tile is 64 x kTY x tile_z
 constexpr int kTX = 64, kTY = 16, kTY2f = 8, kTY2d = 4;
 
 __host__ __device__ inline int div_up(int a, int b) { return (a + b - 1) / b; }

@@ -259,26 +259,33 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 }
 
 // ---------------------------------------------------------------- 2D pass
-// A wave owns a tile of 64 consecutive x and TY rows. Every load of the tile
-// (its TY rows, one halo row above and below, the halo columns, the bonds and
-// the FP64 pressures) is issued up front at a clamped, in-bounds address with
-// no branch on loaded data, so the tile's whole memory traffic is in flight
-// at once; out-of-lattice values are then zeroed with selects. Off the live
-// set r = q = p = 0 in memory, so the arithmetic needs no mask; only stores are
-// restricted to live nodes. x-neighbours come from lane shuffles; lanes 0..TY-1
-// and 64-TY..63 load the halo columns x0-1 and x0+64 (one row each), which
-// shuffles hand to lanes 0 and 63.
+// A workgroup owns a tile of 64 consecutive x and 4 TY rows; wave w holds rows
+// w TY .. w TY + TY - 1. Every load of the tile (the rows, one halo row above
+// and below the workgroup, the halo columns, the bonds and the FP64
+// pressures) is issued up front at a clamped, in-bounds address with no
+// branch on loaded data, so the tile's whole memory traffic is in flight at
+// once; out-of-lattice values are then zeroed with selects. Rows next to
+// another wave's rows get that wave's p' through LDS (one barrier), so only 2
+// rows in 4 TY are re-read. Off the live set r = q = p = 0 in memory, so the
+// arithmetic needs no mask; only stores are restricted to the lattice.
+// x-neighbours come from lane shuffles; lanes 0..TY-1 and 64-TY..63 load the
+// halo columns x0-1 and x0+64 (one row each), which shuffles hand to lanes 0
+// and 63.
 template <typename T>
 struct Tile2D {
-    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;
+    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;   // rows per wave
+    static constexpr int ROWS = TY * (kBlock / kWave);         // rows per workgroup
 };
 
 template <typename T>
-__device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x, int y0, int lane,
-                                          T alpha, T beta, double sa, double (&acc)[kRed])
+__device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x, int yb, int lane,
+                                          int w, T alpha, T beta, double sa, double (&acc)[kRed])
 {
     constexpr int TY = Tile2D<T>::TY;
+    constexpr int NW = kBlock / kWave;
+    __shared__ T edge[2][NW][kWave];   // [0]: first row of each wave, [1]: last row
     const int nx = a.nx, ny = a.ny;
+    const int y0 = yb + w * TY;        // first row of this wave
     const bool valid = x < nx;
     const int xc = valid ? x : nx - 1;
     const T *__restrict__ rs = a.src.r;
@@ -293,57 +300,76 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     auto rowc = [&](int yy) { return yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy); };
 
     // ---- issue every load
-    T d_[TY + 2], r_[TY + 2], q_[TY + 2], p_[TY + 2];
-#pragma unroll
-    for (int j = 0; j < TY + 2; ++j) {
-        const int64_t i = (int64_t)rowc(y0 - 1 + j) * nx + xc;
-        d_[j] = dv[i];
-        r_[j] = rs[i];
-        q_[j] = qs[i];
-        p_[j] = ps[i];
-    }
+    T d_[TY], r_[TY], q_[TY], p_[TY];
     double Pv[TY];
     T gxv[TY], gyv[TY + 1];
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
         const int64_t i = (int64_t)rowc(y0 + j) * nx + xc;
+        d_[j] = dv[i];
+        r_[j] = rs[i];
+        q_[j] = qs[i];
+        p_[j] = ps[i];
         Pv[j] = P[i];
         gxv[j] = gx[i];
         gyv[j + 1] = gy[i];
     }
-    gyv[0] = y0 >= 1 ? gy[(int64_t)(y0 - 1) * nx + xc] : T(0);   // bond below the tile (none at y = 0)
+    gyv[0] = y0 >= 1 ? gy[(int64_t)rowc(y0 - 1) * nx + xc] : T(0);   // bond below the wave (none at y = 0)
+    // the workgroup's outer halo rows: wave 0 the row above, the last wave the row below
+    T ed = T(0), er = T(0), eq = T(0), ep = T(0);
+    if (w == 0 || w == NW - 1) {   // wave-uniform
+        const int yh = w == 0 ? yb - 1 : yb + NW * TY;
+        const bool hrow = valid && yh >= 0 && yh < ny;
+        const int64_t i = (int64_t)rowc(yh) * nx + xc;
+        const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i];
+        if (hrow) {
+            ed = d0;
+            er = r0;
+            eq = q0;
+            ep = p0;
+        }
+    }
     // halo columns: lane l < TY holds (x0-1, y0+l), lane 64-TY+l holds (x0+64, y0+l)
     const bool hleft = lane < TY, hright = lane >= kWave - TY;
-    const int hrow = hleft ? lane : lane - (kWave - TY);
+    const int hr_ = hleft ? lane : lane - (kWave - TY);
     const int x0 = x - lane;
     const int hx = hleft ? x0 - 1 : x0 + kWave;
-    const bool hok = (hleft || hright) && hx >= 0 && hx < nx && y0 + hrow < ny;
+    const bool hok = (hleft || hright) && hx >= 0 && hx < nx && y0 + hr_ < ny;
     T hd = T(0), hr = T(0), hq = T(0), hp = T(0), hg = T(0);
-    if (hok) {
-        const int64_t i = (int64_t)(y0 + hrow) * nx + hx;
-        hd = dv[i];
-        hr = rs[i];
-        hq = qs[i];
-        hp = ps[i];
-        hg = hleft ? gx[i] : T(0);        // bond (x0-1) -> x0 for lane 0
+    {
+        const int64_t i = hok ? (int64_t)(y0 + hr_) * nx + hx : 0;
+        const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i], g0 = gx[i];
+        if (hok) {
+            hd = d0;
+            hr = r0;
+            hq = q0;
+            hp = p0;
+            hg = hleft ? g0 : T(0);        // bond (x0-1) -> x0 for lane 0
+        }
     }
 
-    // ---- p' on all TY + 2 rows, r' and the pressure step on the TY interior rows
-    T pv[TY + 2];
+    // ---- p' on the wave's rows, exchanged with the neighbouring waves
+    T pv[TY + 2];   // rows y0-1 .. y0+TY
 #pragma unroll
-    for (int j = 0; j < TY + 2; ++j) {
-        const int yy = y0 - 1 + j;
-        const bool ok = valid && yy >= 0 && yy < ny;
+    for (int j = 0; j < TY; ++j) {
+        const bool ok = valid && y0 + j < ny;
         const T v = d_[j] * (r_[j] - alpha * q_[j]) + beta * p_[j];
-        pv[j] = ok ? v : T(0);
+        pv[j + 1] = ok ? v : T(0);
     }
-    const T hpv = hd * (hr - alpha * hq) + beta * hp;   // zero when !hok (all inputs zero)
+    edge[0][w][lane] = pv[1];
+    edge[1][w][lane] = pv[TY];
+    const T hv = ed * (er - alpha * eq) + beta * ep;     // zero unless hrow
+    __syncthreads();
+    pv[0] = w == 0 ? hv : edge[1][w - 1][lane];
+    pv[TY + 1] = w == NW - 1 ? hv : edge[0][w + 1][lane];
+    const T hpv = hd * (hr - alpha * hq) + beta * hp;    // zero when !hok
+
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
         const int yy = y0 + j;
         const bool ok = valid && yy < ny;
-        const T dc = ok ? d_[j + 1] : T(0);
-        const T rc = ok ? r_[j + 1] - alpha * q_[j + 1] : T(0);
+        const T dc = ok ? d_[j] : T(0);
+        const T rc = ok ? r_[j] - alpha * q_[j] : T(0);
         const T pc = pv[j + 1];
         // neighbours across x
         T pl = __shfl_up(pc, 1, kWave);
@@ -363,7 +389,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         // live set) so that cache lines are written whole
         if (ok) {
             const int64_t i = (int64_t)yy * nx + x;
-            P[i] = Pv[j] + sa * (double)p_[j + 1];
+            P[i] = Pv[j] + sa * (double)p_[j];
             rd[i] = rc;
             pd[i] = pc;
             qd[i] = qv;
@@ -396,18 +422,19 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
     if (mode == MODE_DONE) return;
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int tile = xcd_remap(lb, a.grid) * (kBlock / kWave) + w;
+    const int tile = xcd_remap(lb, a.grid);      // uniform per workgroup
     const int m = (int)(s->refreshes & 1);
     const double sa = s->sigma * s->alpha;
     if (tile < a.ntiles) {
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         const int x = tx * kWave + lane;
-        const int y0 = ty * Tile2D<T>::TY;
-        const int y1 = min(y0 + Tile2D<T>::TY, a.ny);
+        const int yb = ty * Tile2D<T>::ROWS;
         if (mode == MODE_CG) {
-            cg2d_tile<T>(a, a.P[m], x, y0, lane, (T)s->alpha, (T)s->beta, sa, acc);
+            cg2d_tile<T>(a, a.P[m], x, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
         } else if (x < a.nx) {
             const double sigma_next = s->sigma_next;
+            const int y0 = yb + w * Tile2D<T>::TY;
+            const int y1 = min(y0 + Tile2D<T>::TY, a.ny);
             for (int yy = y0; yy < y1; ++yy)
                 refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
         }

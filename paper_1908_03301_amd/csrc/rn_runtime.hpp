@@ -143,6 +143,15 @@ private:
     int64_t launches_ = 0;
     int chunk_ = 16;
     int peak_active_ = 0;                   // most networks that shared one launch
+    // hipGraph of kGraphRounds pass rounds for the current block tables,
+    // replayed for the bulk of each chunk (the round count is even, so the
+    // parities baked into the graph stay valid from replay to replay)
+    static constexpr int kGraphRounds = 8;
+    bool use_graph_ = false;
+    hipGraphExec_t gexec_ = nullptr;
+    int graph_parity_ = -1;
+    int launch_rounds(int rounds, hipStream_t st, std::string *err);
+    int capture(hipStream_t st, std::string *err);
 };
 
 }  // namespace rn

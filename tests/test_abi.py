@@ -118,3 +118,14 @@ def test_null_context_is_rejected(lib):
     assert lib.rn_solve(None, C.byref(_prob().c), None, C.byref(res)) == B.RN_EINVAL
     assert lib.rn_build_mask(None, C.byref(_prob().c), None) == B.RN_EINVAL
     assert lib.rn_destroy(None) == B.RN_OK
+
+
+def test_batch_and_serve_argument_checks(lib):
+    """rn_solve_batch / rn_submit / rn_poll / rn_stats reject bad arguments before any device call."""
+    res = (B.rn_result * 2)()
+    probs = (B.rn_problem * 2)(_prob().c, _prob().c)
+    assert lib.rn_solve_batch(None, 2, probs, None, 0, res) == B.RN_EINVAL
+    t = C.c_uint64(0)
+    assert lib.rn_submit(None, C.byref(_prob().c), None, C.byref(t)) == B.RN_EINVAL
+    assert lib.rn_poll(None, 1, C.byref(B.rn_result())) == B.RN_EINVAL
+    assert lib.rn_stats(None, C.byref(B.rn_stats_t())) == B.RN_EINVAL

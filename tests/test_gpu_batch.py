@@ -193,3 +193,35 @@ def test_eagain_then_ok(ctx):
         assert st == B.RN_OK and r.converged and r.iters > 0
     finally:
         c.close()
+
+
+def test_graph_replay_bit_identical(solos):
+    """With RN_GRAPHS=1 the pass rounds of each chunk are replayed from a
+    captured hipGraph; every network must give the bits of direct launches."""
+    import os
+    sets = mixed_set()
+    old = os.environ.get("RN_GRAPHS")
+    os.environ["RN_GRAPHS"] = "1"
+    try:
+        c = B.Context(0)
+    finally:
+        if old is None:
+            del os.environ["RN_GRAPHS"]
+        else:
+            os.environ["RN_GRAPHS"] = old
+    try:
+        for i in (0, 2, 6):   # 2D FP64, 3D mixed, the 128^2 workload
+            net, prec, tol = sets[i]
+            say(f"graph replay: solo {i} dim={net.dim} shape={net.shape}")
+            r, P = solo(c, net, prec, tol)
+            same(solos[i][0], r)
+            assert P.tobytes() == solos[i][1].tobytes()
+        Ps = [np.zeros(net.shape) for net, _, _ in sets]
+        probs = [B.problem(net, p_out=P) for (net, _, _), P in zip(sets, Ps)]
+        say("graph replay: batch")
+        res = c.solve_batch(probs, [B.opts(p, t) for _, p, t in sets])
+        for (r_solo, P_solo), r, P in zip(solos, res, Ps):
+            same(r_solo, r)
+            assert P.tobytes() == P_solo.tobytes()
+    finally:
+        c.close()
