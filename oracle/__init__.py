@@ -50,7 +50,7 @@ def _load():
         dp = C.POINTER(C.c_double)
         u8p = C.POINTER(C.c_uint8)
         i64 = C.c_int64
-        common = [C.c_int, i64, i64, i64, C.c_int, dp, dp, dp]
+        common = [C.c_int, i64, i64, i64, C.c_int, C.c_int, dp, dp, dp]
         lib.rno_mask_bfs.argtypes = common + [u8p, C.POINTER(i64)]
         lib.rno_mask_uf.argtypes = common + [u8p, C.POINTER(i64)]
         lib.rno_solve.argtypes = common + [C.c_double, i64, dp, u8p, C.POINTER(_Result)]
@@ -67,11 +67,12 @@ def _dptr(a: Optional[np.ndarray]):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-def _args(dim: int, nx: int, ny: int, nz: int, axis: int, g: Sequence[np.ndarray]):
+def _args(dim: int, nx: int, ny: int, nz: int, axis: int, periodic: bool, g: Sequence[np.ndarray]):
     gs = [np.ascontiguousarray(a, dtype=np.float64) for a in g]
     while len(gs) < 3:
         gs.append(None)
-    return gs, [int(dim), int(nx), int(ny), int(nz), int(axis), _dptr(gs[0]), _dptr(gs[1]), _dptr(gs[2])]
+    return gs, [int(dim), int(nx), int(ny), int(nz), int(axis), int(bool(periodic)),
+                _dptr(gs[0]), _dptr(gs[1]), _dptr(gs[2])]
 
 
 class OracleError(RuntimeError):
@@ -96,13 +97,14 @@ class OracleResult:
 
 
 def _net_args(net):
-    return net.dim, net.nx, net.ny, net.nz, net.axis, net.g
+    """(dim, nx, ny, nz, axis, periodic, g) of a Network; `periodic` wraps the
+    directions other than the flow axis (the side condition of Sec. II)."""
+    return net.dim, net.nx, net.ny, net.nz, net.axis, bool(getattr(net, "periodic", False)), net.g
 
 
 def mask_bfs(net) -> tuple:
     """(mask uint8 array of the node shape, n_live) by two breadth-first searches."""
-    dim, nx, ny, nz, axis, g = _net_args(net)
-    keep, a = _args(dim, nx, ny, nz, axis, g)
+    keep, a = _args(*_net_args(net))
     out = np.zeros(net.shape, dtype=np.uint8)
     nl = C.c_int64(0)
     st = _load().rno_mask_bfs(*a, out.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nl))
@@ -113,8 +115,7 @@ def mask_bfs(net) -> tuple:
 
 def mask_uf(net) -> tuple:
     """Same mask by an independent sequential union-find."""
-    dim, nx, ny, nz, axis, g = _net_args(net)
-    keep, a = _args(dim, nx, ny, nz, axis, g)
+    keep, a = _args(*_net_args(net))
     out = np.zeros(net.shape, dtype=np.uint8)
     nl = C.c_int64(0)
     st = _load().rno_mask_uf(*a, out.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nl))
@@ -126,8 +127,7 @@ def mask_uf(net) -> tuple:
 def solve(net, tol: float = 1e-12, max_iter: int = 1_000_000, want_pressure: bool = True,
           want_mask: bool = False, raise_on_error: bool = True) -> OracleResult:
     """Jacobi-PCG to ||b - A x|| <= tol ||b|| (FP64), then fluxes, energy G and K."""
-    dim, nx, ny, nz, axis, g = _net_args(net)
-    keep, a = _args(dim, nx, ny, nz, axis, g)
+    keep, a = _args(*_net_args(net))
     P = np.zeros(net.shape, dtype=np.float64) if want_pressure else None
     M = np.zeros(net.shape, dtype=np.uint8) if want_mask else None
     res = _Result()
@@ -160,8 +160,7 @@ class PressureCheck:
 
 def check_pressure(net, P: np.ndarray) -> PressureCheck:
     """Evaluate, with the oracle's own mask and operator, a given full pressure field."""
-    dim, nx, ny, nz, axis, g = _net_args(net)
-    keep, a = _args(dim, nx, ny, nz, axis, g)
+    keep, a = _args(*_net_args(net))
     Pc = np.ascontiguousarray(P, dtype=np.float64).reshape(net.shape)
     out = np.zeros(10, dtype=np.float64)
     st = _load().rno_check_pressure(*a, _dptr(Pc), _dptr(out))

@@ -27,10 +27,18 @@
  * to i + e_k (k = 0,1,2 for x,y,z); entries whose neighbour is off the
  * lattice are ignored.
  *
+ * Side boundaries: no flow by default. With `periodic` set, every direction
+ * other than the flow axis wraps around (Sec. II imposes the pressure drop
+ * along one direction and periodic conditions along the other): the entry
+ * g[k][i] on the last plane along k is then the bond to the first plane. A
+ * direction of extent 1 has no bonds along it either way.
+ *
  * Parity status of each function: every function here is pinned by the CPU
  * tests (closed forms, dense direct solves, brute-force connectivity, planar
- * duality, conservation identities); iteration counts are reported but
- * parity-unpinned (the paper prints none).
+ * duality, conservation identities; for periodic sides also a hand-solved
+ * path across the wrap and invariance under translation along a wrapped
+ * direction); iteration counts are reported but parity-unpinned (the paper
+ * prints none).
  */
 #include <math.h>
 #include <stdint.h>
@@ -51,6 +59,7 @@ typedef struct {
 
 typedef struct {
     int dim, axis;
+    int wrap[3];       /* direction k wraps around (periodic sides, extent >= 2) */
     int64_t n[3];      /* nx, ny, nz */
     int64_t stride[3]; /* 1, nx, nx*ny */
     int64_t N;
@@ -61,19 +70,30 @@ typedef struct {
 
 static int64_t coord(const lat_t *L, int64_t i, int k) { return (i / L->stride[k]) % L->n[k]; }
 
-/* Neighbour of node i across direction k and sign s (+1/-1); returns -1 off
- * the lattice. *gij receives the bond conductance (0 when off-lattice). */
+/* Neighbour across direction k and sign s (+1/-1) of the node with index i
+ * and coordinates c; returns -1 when there is none. *gij receives the bond
+ * conductance (0 when there is no neighbour). Across a periodic direction the
+ * last plane's +1 neighbour is the first plane, through the last plane's own
+ * bond entry. */
+static int64_t nbr_at(const lat_t *L, const int64_t c[3], int64_t i, int k, int s, double *gij)
+{
+    const int64_t n = L->n[k], st = L->stride[k];
+    if (s > 0) {
+        if (c[k] + 1 < n) { *gij = L->g[k][i]; return i + st; }
+        if (L->wrap[k]) { *gij = L->g[k][i]; return i - (n - 1) * st; }
+        *gij = 0.0;
+        return -1;
+    }
+    if (c[k] > 0) { *gij = L->g[k][i - st]; return i - st; }
+    if (L->wrap[k]) { *gij = L->g[k][i + (n - 1) * st]; return i + (n - 1) * st; }
+    *gij = 0.0;
+    return -1;
+}
+
 static int64_t nbr(const lat_t *L, int64_t i, int k, int s, double *gij)
 {
-    int64_t c = coord(L, i, k);
-    if (s > 0) {
-        if (c + 1 >= L->n[k]) { *gij = 0.0; return -1; }
-        *gij = L->g[k][i];
-        return i + L->stride[k];
-    }
-    if (c == 0) { *gij = 0.0; return -1; }
-    *gij = L->g[k][i - L->stride[k]];
-    return i - L->stride[k];
+    const int64_t c[3] = {coord(L, i, 0), coord(L, i, 1), coord(L, i, 2)};
+    return nbr_at(L, c, i, k, s, gij);
 }
 
 /* Face classification along the flow axis: 0 interior, 1 inlet, 2 outlet. */
@@ -85,7 +105,7 @@ static int face_of(const lat_t *L, int64_t i)
     return 0;
 }
 
-static int setup(lat_t *L, int dim, int64_t nx, int64_t ny, int64_t nz, int axis,
+static int setup(lat_t *L, int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
                  const double *g0, const double *g1, const double *g2)
 {
     if (dim != 2 && dim != 3) return RNO_EINVAL;
@@ -99,10 +119,12 @@ static int setup(lat_t *L, int dim, int64_t nx, int64_t ny, int64_t nz, int axis
     L->N = nx * ny * nz;
     if (L->n[axis] < 2) return RNO_EINVAL;
     L->g[0] = g0; L->g[1] = g1; L->g[2] = (dim == 3) ? g2 : NULL;
+    if (periodic != 0 && periodic != 1) return RNO_EINVAL;
+    for (int k = 0; k < 3; ++k) L->wrap[k] = periodic && k < dim && k != axis && L->n[k] >= 2;
     for (int k = 0; k < dim; ++k) {
         if (!L->g[k]) return RNO_EINVAL;
         for (int64_t i = 0; i < L->N; ++i) {
-            if (coord(L, i, k) + 1 >= L->n[k]) continue; /* off-lattice entry: ignored */
+            if (coord(L, i, k) + 1 >= L->n[k] && !L->wrap[k]) continue; /* off-lattice entry: ignored */
             double v = L->g[k][i];
             if (!(v >= 0.0) || isinf(v)) return RNO_EINVAL;  /* negative, NaN or Inf */
         }
@@ -165,12 +187,12 @@ static int mask_bfs(const lat_t *L, uint8_t *mask, int64_t *n_live)
     return RNO_OK;
 }
 
-int rno_mask_bfs(int dim, int64_t nx, int64_t ny, int64_t nz, int axis,
+int rno_mask_bfs(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
                  const double *g0, const double *g1, const double *g2,
                  uint8_t *mask_out, int64_t *n_live_out)
 {
     lat_t L;
-    int st = setup(&L, dim, nx, ny, nz, axis, g0, g1, g2);
+    int st = setup(&L, dim, nx, ny, nz, axis, periodic, g0, g1, g2);
     if (st) return st;
     return mask_bfs(&L, mask_out, n_live_out);
 }
@@ -187,12 +209,12 @@ static int64_t uf_find(int64_t *par, int64_t a)
     return r;
 }
 
-int rno_mask_uf(int dim, int64_t nx, int64_t ny, int64_t nz, int axis,
+int rno_mask_uf(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
                 const double *g0, const double *g1, const double *g2,
                 uint8_t *mask_out, int64_t *n_live_out)
 {
     lat_t L;
-    int st = setup(&L, dim, nx, ny, nz, axis, g0, g1, g2);
+    int st = setup(&L, dim, nx, ny, nz, axis, periodic, g0, g1, g2);
     if (st) return st;
     int64_t *par = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.N);
     int64_t *sz = (int64_t *)malloc(sizeof(int64_t) * (size_t)L.N);
@@ -257,22 +279,19 @@ static double pdot(const double *a, const double *b, int64_t n)
  * with d_i the sum of the conductances of all occupied bonds at i. */
 static void apply_A(const lat_t *L, const uint8_t *mask, const double *d, const double *v, double *out)
 {
-    const int64_t nx = L->n[0], ny = L->n[1], nz = L->n[2];
-    const int64_t sy = L->stride[1], sz = L->stride[2];
-    for (int64_t z = 0; z < nz; ++z)
-        for (int64_t y = 0; y < ny; ++y)
-            for (int64_t x = 0; x < nx; ++x) {
-                int64_t i = x + sy * y + sz * z;
+    int64_t c[3];
+    for (c[2] = 0; c[2] < L->n[2]; ++c[2])
+        for (c[1] = 0; c[1] < L->n[1]; ++c[1])
+            for (c[0] = 0; c[0] < L->n[0]; ++c[0]) {
+                const int64_t i = c[0] + L->stride[1] * c[1] + L->stride[2] * c[2];
                 if (mask[i] != 3) { out[i] = 0.0; continue; }
                 double s = d[i] * v[i];
-                if (x > 0 && mask[i - 1] == 3) s -= L->g[0][i - 1] * v[i - 1];
-                if (x + 1 < nx && mask[i + 1] == 3) s -= L->g[0][i] * v[i + 1];
-                if (y > 0 && mask[i - sy] == 3) s -= L->g[1][i - sy] * v[i - sy];
-                if (y + 1 < ny && mask[i + sy] == 3) s -= L->g[1][i] * v[i + sy];
-                if (L->dim == 3) {
-                    if (z > 0 && mask[i - sz] == 3) s -= L->g[2][i - sz] * v[i - sz];
-                    if (z + 1 < nz && mask[i + sz] == 3) s -= L->g[2][i] * v[i + sz];
-                }
+                for (int k = 0; k < L->dim; ++k)
+                    for (int sg = -1; sg <= 1; sg += 2) {
+                        double gij;
+                        const int64_t j = nbr_at(L, c, i, k, sg, &gij);
+                        if (j >= 0 && mask[j] == 3) s -= gij * v[j];
+                    }
                 out[i] = s;
             }
 }
@@ -354,12 +373,12 @@ static double cross_section(const lat_t *L)
  * equals sum over bonds g (dP)^2 and whose error is quadratic in the solution
  * error, and K from Eq. 4.
  */
-int rno_solve(int dim, int64_t nx, int64_t ny, int64_t nz, int axis,
+int rno_solve(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
               const double *g0, const double *g1, const double *g2,
               double tol, int64_t max_iter, double *p_out, uint8_t *mask_out, rno_result *res)
 {
     lat_t L;
-    int st = setup(&L, dim, nx, ny, nz, axis, g0, g1, g2);
+    int st = setup(&L, dim, nx, ny, nz, axis, periodic, g0, g1, g2);
     if (st) return st;
     if (!(tol > 0.0) || max_iter < 0 || !res) return RNO_EINVAL;
     memset(res, 0, sizeof(*res));
@@ -458,12 +477,12 @@ done:
  *   0 ||b - A x||, 1 ||b||, 2 Q_in, 3 Q_out, 4 G_E, 5 K_E, 6 min P_live,
  *   7 max P_live, 8 sum (A x - b), 9 n_live.
  */
-int rno_check_pressure(int dim, int64_t nx, int64_t ny, int64_t nz, int axis,
+int rno_check_pressure(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
                        const double *g0, const double *g1, const double *g2,
                        const double *P_in, double *out)
 {
     lat_t L;
-    int st = setup(&L, dim, nx, ny, nz, axis, g0, g1, g2);
+    int st = setup(&L, dim, nx, ny, nz, axis, periodic, g0, g1, g2);
     if (st) return st;
     size_t N = (size_t)L.N;
     uint8_t *mask = (uint8_t *)malloc(N);

@@ -50,6 +50,7 @@ class Network:
     g: List[np.ndarray]                      # dim arrays, node-shaped, float64, C-contiguous
     axis: int = 0
     meta: dict = field(default_factory=dict)
+    periodic: bool = False                   # directions other than the flow axis wrap around
 
     @property
     def n(self) -> int:
@@ -60,7 +61,16 @@ class Network:
         return (self.ny, self.nx) if self.dim == 2 else (self.nz, self.ny, self.nx)
 
     def with_axis(self, axis: int) -> "Network":
-        return Network(self.dim, self.nx, self.ny, self.nz, self.g, axis, dict(self.meta))
+        return Network(self.dim, self.nx, self.ny, self.nz, self.g, axis, dict(self.meta), self.periodic)
+
+    def with_periodic(self, periodic: bool = True) -> "Network":
+        """Same bond arrays with periodic (or no-flow) side boundaries.
+
+        The last-plane entries of the transverse bond arrays are the wrap
+        bonds of a periodic network; the generators below draw them when
+        called with ``periodic=True`` and zero them otherwise.
+        """
+        return Network(self.dim, self.nx, self.ny, self.nz, self.g, self.axis, dict(self.meta), bool(periodic))
 
 
 def node_shape(dim: int, nx: int, ny: int, nz: int = 1) -> Tuple[int, ...]:
@@ -69,17 +79,19 @@ def node_shape(dim: int, nx: int, ny: int, nz: int = 1) -> Tuple[int, ...]:
     return (nz, ny, nx)
 
 
+def clear_edge(a: np.ndarray, k: int) -> np.ndarray:
+    """Copy of bond array ``a`` of direction k with its last-plane entries zeroed."""
+    a = np.array(a, dtype=np.float64, copy=True, order="C")
+    ax = a.ndim - 1 - k                      # numpy axis of lattice direction k (x is last)
+    sl = [slice(None)] * a.ndim
+    sl[ax] = -1
+    a[tuple(sl)] = 0.0
+    return a
+
+
 def clear_edge_bonds(g: List[np.ndarray]) -> List[np.ndarray]:
     """Zero the entries of bond array k whose neighbour ``i + e_k`` is outside the lattice."""
-    out = []
-    for k, a in enumerate(g):
-        a = np.array(a, dtype=np.float64, copy=True, order="C")
-        ax = a.ndim - 1 - k                  # numpy axis of lattice direction k (x is last)
-        sl = [slice(None)] * a.ndim
-        sl[ax] = -1
-        a[tuple(sl)] = 0.0
-        out.append(a)
-    return out
+    return [clear_edge(a, k) for k, a in enumerate(g)]
 
 
 def edge_valid(dim: int, shape: Tuple[int, ...], k: int) -> np.ndarray:
@@ -127,23 +139,30 @@ def fbm_field(shape: Sequence[int], H: float, rng: np.random.Generator,
     return (field_ - field_.mean()) / sd
 
 
-def bonds_from_node_field(phi: np.ndarray, sigma: float) -> List[np.ndarray]:
-    """ln g of a bond = sigma * (mean of its two end-node field values)."""
+def bonds_from_node_field(phi: np.ndarray, sigma: float, periodic: bool = False) -> List[np.ndarray]:
+    """ln g of a bond = sigma * (mean of its two end-node field values).
+
+    The field is periodic, so the last-plane entry of direction k joins the
+    last and the first plane; it is kept for a periodic lattice, else zeroed.
+    """
     dim = phi.ndim
     out = []
     for k in range(dim):
         ax = dim - 1 - k
-        nb = np.roll(phi, -1, axis=ax)       # value at i + e_k (wrapped entries are cleared below)
+        nb = np.roll(phi, -1, axis=ax)       # value at i + e_k, wrapped on the last plane
         out.append(np.exp(sigma * 0.5 * (phi + nb)))
-    return clear_edge_bonds(out)
+    return out if periodic else clear_edge_bonds(out)
 
 
 def iid_lognormal(dim: int, nx: int, ny: int, nz: int, sigma: float,
-                  rng: np.random.Generator, mu: float = 0.0) -> List[np.ndarray]:
-    """ln g ~ N(mu, sigma^2) independently per bond (direction 0 first, then 1, then 2)."""
+                  rng: np.random.Generator, mu: float = 0.0, periodic: bool = False) -> List[np.ndarray]:
+    """ln g ~ N(mu, sigma^2) independently per bond (direction 0 first, then 1, then 2).
+
+    Every entry is drawn; the last-plane entries are zeroed unless ``periodic``.
+    """
     shape = node_shape(dim, nx, ny, nz)
     g = [np.exp(mu + sigma * rng.standard_normal(shape)) for _ in range(dim)]
-    return clear_edge_bonds(g)
+    return [np.ascontiguousarray(a) for a in g] if periodic else clear_edge_bonds(g)
 
 
 def dilute_iid(g: List[np.ndarray], occupancy: float, rng: np.random.Generator) -> List[np.ndarray]:
@@ -155,18 +174,21 @@ def dilute_iid(g: List[np.ndarray], occupancy: float, rng: np.random.Generator) 
     return out
 
 
-def dilute_rank(g: List[np.ndarray], q: float) -> List[np.ndarray]:
-    """Remove the fraction ``q`` of in-lattice bonds with the smallest conductance.
+def dilute_rank(g: List[np.ndarray], q: float, wrap: Optional[Sequence[bool]] = None) -> List[np.ndarray]:
+    """Remove the fraction ``q`` of lattice bonds with the smallest conductance.
 
     Correlated dilution of Sec. VI.B: sort all bonds by conductance and cut the
     lowest ``floor(q * n_bonds)``; ties are broken by bond order (direction,
-    then node index) so the result is reproducible.
+    then node index) so the result is reproducible. ``wrap[k]`` counts the
+    last-plane entries of direction k as bonds (periodic sides).
     """
     dim = len(g)
     shape = g[0].shape
     vals, keys = [], []
     for k, a in enumerate(g):
         valid = edge_valid(dim, shape, k).ravel()
+        if wrap is not None and wrap[k]:
+            valid = np.ones_like(valid)
         idx = np.nonzero(valid)[0]
         vals.append(a.ravel()[idx])
         keys.append(np.stack([np.full(idx.size, k), idx], axis=1))
@@ -184,42 +206,52 @@ def dilute_rank(g: List[np.ndarray], q: float) -> List[np.ndarray]:
 
 # ----------------------------------------------------------------------------- workloads
 
-def uniform_network(dim: int, nx: int, ny: int, nz: int = 1, g0: float = 1.0, axis: int = 0) -> Network:
+def uniform_network(dim: int, nx: int, ny: int, nz: int = 1, g0: float = 1.0, axis: int = 0,
+                    periodic: bool = False) -> Network:
     shape = node_shape(dim, nx, ny, nz)
-    g = clear_edge_bonds([np.full(shape, g0) for _ in range(dim)])
-    return Network(dim, nx, ny, nz if dim == 3 else 1, g, axis, {"kind": "uniform", "g0": g0})
+    g = [np.full(shape, g0) for _ in range(dim)]
+    if not periodic:
+        g = clear_edge_bonds(g)
+    return Network(dim, nx, ny, nz if dim == 3 else 1, g, axis, {"kind": "uniform", "g0": g0}, periodic)
 
 
 def iid_network(dim: int, nx: int, ny: int, nz: int = 1, sigma: float = 1.0,
-                occupancy: float = 1.0, index: int = 0, axis: int = 0) -> Network:
+                occupancy: float = 1.0, index: int = 0, axis: int = 0, periodic: bool = False) -> Network:
     rng = rng_for(index)
-    g = iid_lognormal(dim, nx, ny, nz, sigma, rng)
+    g = iid_lognormal(dim, nx, ny, nz, sigma, rng, periodic=periodic)
     if occupancy < 1.0:
         g = dilute_iid(g, occupancy, rng)
     return Network(dim, nx, ny, nz if dim == 3 else 1, g, axis,
-                   {"kind": "iid", "sigma": sigma, "occupancy": occupancy, "index": index})
+                   {"kind": "iid", "sigma": sigma, "occupancy": occupancy, "index": index}, periodic)
 
 
 def fbm_network(dim: int, nx: int, ny: int, nz: int = 1, H: float = 0.7, sigma: float = 1.0,
                 occupancy: float = 1.0, index: int = 0, axis: int = 0,
-                beta: Optional[Sequence[float]] = None, rank_q: Optional[float] = None) -> Network:
-    """FBM log-normal network: node field -> bond ln g -> optional dilution."""
+                beta: Optional[Sequence[float]] = None, rank_q: Optional[float] = None,
+                periodic: bool = False) -> Network:
+    """FBM log-normal network: node field -> bond ln g -> optional dilution.
+
+    With ``periodic`` the sides wrap around (Sec. II); rank dilution then
+    counts the wrap bonds of the directions other than ``axis``.
+    """
     rng = rng_for(index)
     shape = node_shape(dim, nx, ny, nz)
     phi = fbm_field(shape, H, rng, beta=beta)
-    g = bonds_from_node_field(phi, sigma)
+    g = bonds_from_node_field(phi, sigma, periodic=periodic)
     if rank_q is not None:
-        g = dilute_rank(g, rank_q)
+        wrap = [periodic and k != axis for k in range(dim)]
+        g = dilute_rank([a if wrap[k] else clear_edge(a, k) for k, a in enumerate(g)], rank_q, wrap)
     elif occupancy < 1.0:
         g = dilute_iid(g, occupancy, rng)
     return Network(dim, nx, ny, nz if dim == 3 else 1, g, axis,
                    {"kind": "fbm", "H": H, "sigma": sigma, "occupancy": occupancy,
-                    "index": index, "beta": None if beta is None else list(beta), "rank_q": rank_q})
+                    "index": index, "beta": None if beta is None else list(beta), "rank_q": rank_q},
+                   periodic)
 
 
 def stratified_network(n: int, H: float = 0.8, sigma: float = 2.0, occupancy: float = 1.0,
                        index: int = 0, axis: int = 0, nx: Optional[int] = None,
-                       ny: Optional[int] = None, nz: Optional[int] = None) -> Network:
+                       ny: Optional[int] = None, nz: Optional[int] = None, periodic: bool = False) -> Network:
     """3D layered medium: ln g follows a 1D FBM profile phi(z) (H, standardised, times sigma).
 
     x- and y-bonds in layer z get ``sigma * phi[z]``; the z-bond from layer z to
@@ -232,14 +264,16 @@ def stratified_network(n: int, H: float = 0.8, sigma: float = 2.0, occupancy: fl
     phi = fbm_field((nz,), H, rng)
     shape = (nz, ny, nx)
     lg_xy = (sigma * phi)[:, None, None] * np.ones(shape)
-    phi_up = np.concatenate([phi[1:], phi[-1:]])
+    phi_up = np.roll(phi, -1)                # the last layer's z-bond wraps to layer 0
     lg_z = (sigma * 0.5 * (phi + phi_up))[:, None, None] * np.ones(shape)
-    g = clear_edge_bonds([np.exp(lg_xy), np.exp(lg_xy), np.exp(lg_z)])
+    g = [np.exp(lg_xy), np.exp(lg_xy), np.exp(lg_z)]
+    if not periodic:
+        g = clear_edge_bonds(g)
     if occupancy < 1.0:
         g = dilute_iid(g, occupancy, rng)
     return Network(3, nx, ny, nz, g, axis,
                    {"kind": "stratified", "H": H, "sigma": sigma, "occupancy": occupancy,
-                    "index": index, "phi": phi})
+                    "index": index, "phi": phi}, periodic)
 
 
 # Named workloads: the five cases the benchmark and the parity tests use.

@@ -14,18 +14,32 @@ from paper_1908_03301_amd.inputs import Network
 
 
 def bond_list(net: Network):
-    """All in-lattice bonds as (i, j, g) with i < j (flat node indices)."""
+    """All lattice bonds as (i, j, g) (flat node indices; i < j except wrap bonds).
+
+    On a periodic network every direction other than the flow axis with at
+    least 2 planes also has the wrap bonds last plane -> first plane, carried
+    by the last plane's entries (on 2 planes they parallel the inner bonds).
+    """
     idx = np.arange(net.n).reshape(net.shape)
     I, J, Gs = [], [], []
     for k in range(net.dim):
         ax = net.dim - 1 - k
+        n_k = net.shape[ax]
         sl_a = [slice(None)] * net.dim
         sl_b = [slice(None)] * net.dim
-        sl_a[ax] = slice(0, net.shape[ax] - 1)
-        sl_b[ax] = slice(1, net.shape[ax])
+        sl_a[ax] = slice(0, n_k - 1)
+        sl_b[ax] = slice(1, n_k)
         I.append(idx[tuple(sl_a)].ravel())
         J.append(idx[tuple(sl_b)].ravel())
         Gs.append(np.asarray(net.g[k])[tuple(sl_a)].ravel())
+        if getattr(net, "periodic", False) and k != net.axis and n_k >= 2:
+            last = [slice(None)] * net.dim
+            first = [slice(None)] * net.dim
+            last[ax] = n_k - 1
+            first[ax] = 0
+            I.append(idx[tuple(last)].ravel())
+            J.append(idx[tuple(first)].ravel())
+            Gs.append(np.asarray(net.g[k])[tuple(last)].ravel())
     return np.concatenate(I), np.concatenate(J), np.concatenate(Gs)
 
 
