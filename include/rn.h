@@ -7,7 +7,9 @@
  * percolation dilution of Sec. V-VI). Mass balance sum_j g_ij (P_j - P_i) = 0
  * holds at every interior node; the first node plane along the flow axis
  * (inlet face) is held at P = 1, the last plane (outlet face) at P = 0, and
- * no flow crosses the side faces. The library returns the total flux Q and
+ * either no flow crosses the side faces or, with RN_PERIODIC, the directions
+ * other than the flow axis wrap around (the periodic side condition of
+ * Sec. II). The library returns the total flux Q and
  * Darcy's K (Eq. 4) = Q (n_axis - 1) / S, with S the product of the extents
  * other than the flow axis (unit viscosity, bond length and pressure drop).
  *
@@ -23,9 +25,10 @@
  *   - Lattice layout: node i = x + nx*(y + ny*z) (x fastest). g[k] is an
  *     array of nx*ny*nz doubles; g[k][i] is the bond from node i to its
  *     neighbour i + e_k (k = 0,1,2 for x,y,z). Entries whose neighbour lies
- *     past the lattice edge are ignored (any value, even NaN). g[2] must be
- *     NULL in 2D. Every other entry must be finite and >= 0 (RN_EINVAL
- *     otherwise).
+ *     past the lattice edge are ignored (any value, even NaN), except on a
+ *     periodic direction, where the last plane's entry is the bond to the
+ *     first plane. g[2] must be NULL in 2D. Every other entry must be finite
+ *     and >= 0 (RN_EINVAL otherwise).
  *   - Pointers in rn_problem live in the memory space named by its `mem`
  *     field: RN_MEM_HOST (pageable or pinned host memory) or RN_MEM_DEVICE
  *     (device memory on the context's GPU, e.g. a torch tensor's data_ptr).
@@ -64,6 +67,12 @@ extern "C" {
 #define RN_MEM_HOST 0
 #define RN_MEM_DEVICE 1
 
+/* rn_problem.flags */
+#define RN_PERIODIC 1  /* periodic sides (Sec. II): every direction k other than the flow axis
+                          with extent >= 2 wraps around; g[k][i] on the last plane along k is
+                          the bond to the node on the first plane. Without it the sides are
+                          no-flow and those entries are ignored. */
+
 typedef struct rn_ctx rn_ctx;
 
 /* One network: lattice, flow axis, conductances, optional outputs. */
@@ -77,7 +86,7 @@ typedef struct {
                            inlet only, else 0 */
     uint8_t *mask_out;  /* nullable, nx*ny*nz bytes: connectivity mask (rn_build_mask) */
     int32_t mem;        /* RN_MEM_HOST or RN_MEM_DEVICE for g, p_out and mask_out */
-    int32_t reserved;   /* must be 0 */
+    int32_t flags;      /* 0 (no-flow sides) or RN_PERIODIC; other bits: RN_EINVAL */
 } rn_problem;
 
 /* Solver options; rn_opts_default() fills the defaults. */
@@ -145,8 +154,8 @@ const char *rn_last_error(rn_ctx *ctx);
 
 /*
  * Check a problem and options without touching a device: shapes, axis,
- * pointers, reserved fields, options and, for RN_MEM_HOST, every in-lattice
- * conductance (finite, >= 0). opts may be NULL (defaults). Returns RN_OK or
+ * pointers, flags, reserved fields, options and, for RN_MEM_HOST, every
+ * conductance the lattice uses (finite, >= 0). opts may be NULL (defaults). Returns RN_OK or
  * RN_EINVAL; the same checks open rn_solve and rn_build_mask.
  */
 int rn_validate(const rn_problem *prob, const rn_opts *opts);

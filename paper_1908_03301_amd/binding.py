@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "librn.so")
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ENOCONV, RN_ENUMERIC, RN_EDEVICE, RN_EAGAIN, RN_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 RN_FP64, RN_MIXED = 0, 1
 RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
+RN_PERIODIC = 1
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
@@ -30,7 +31,7 @@ class rn_problem(C.Structure):
     _fields_ = [("dim", C.c_int32), ("axis", C.c_int32),
                 ("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64),
                 ("g", C.c_void_p * 3), ("p_out", C.c_void_p), ("mask_out", C.c_void_p),
-                ("mem", C.c_int32), ("reserved", C.c_int32)]
+                ("mem", C.c_int32), ("flags", C.c_int32)]
 
 
 class rn_opts(C.Structure):
@@ -126,17 +127,22 @@ class Problem:
 
 
 def problem(net=None, *, dim=None, nx=None, ny=None, nz=1, axis=0, g: Optional[Sequence] = None,
-            p_out=None, mask_out=None) -> Problem:
+            p_out=None, mask_out=None, periodic: Optional[bool] = None) -> Problem:
     """Build an rn_problem from a Network (inputs.Network) or explicit fields.
 
     ``g`` entries are float64 numpy arrays (host) or float64 CUDA tensors
     (device); ``p_out`` / ``mask_out`` must be in the same memory space.
+    ``periodic`` (default: the Network's own setting, else False) sets
+    RN_PERIODIC: the directions other than the flow axis wrap around.
     """
     if net is not None:
         dim, nx, ny, nz, axis, g = net.dim, net.nx, net.ny, net.nz, net.axis, net.g
+        if periodic is None:
+            periodic = bool(getattr(net, "periodic", False))
     keep: List = []
     pr = rn_problem()
     pr.dim, pr.axis, pr.nx, pr.ny, pr.nz = int(dim), int(axis), int(nx), int(ny), int(nz)
+    pr.flags = RN_PERIODIC if periodic else 0
     device = any(_is_torch(a) for a in g if a is not None)
     pr.mem = RN_MEM_DEVICE if device else RN_MEM_HOST
     for k in range(3):

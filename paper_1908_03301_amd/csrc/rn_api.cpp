@@ -461,7 +461,7 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
     hipError_t he;
     char *base = (char *)ctx->pool.alloc(total, &he);
     if (!base) return RN_ENOMEM;
-    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, (int64_t)n};
+    const Lat lat = make_lat(p);
     const double *gd[3] = {nullptr, nullptr, nullptr};
     auto done = [&](int r) {
         (void)hipStreamSynchronize(ctx->stream);

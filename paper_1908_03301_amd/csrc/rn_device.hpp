@@ -42,8 +42,7 @@ struct Scalars {
     double last_check;  // true relative residual at the previous failed convergence check
     double est_check;   // predicted relative residual that triggered the pending check
     double Q_in, Q_out, xr;  // fluxes and x.(b - A x) from the last refresh
-    uint32_t ticket;    // workgroups finished in the current launch
-    uint32_t pad_;
+    uint32_t pad1_, pad2_;
 };
 
 // What the host polls (copied to pinned memory after each chunk of launches).
@@ -54,6 +53,18 @@ struct Status {
 };
 
 constexpr int kRed = 5;          // partial sums per workgroup
+// Completion tickets of a pass: workgroup lb counts on the counter of its
+// group lb % groups (groups = a power of two up to kGroupsMax, about one per
+// 64 workgroups); the last of each group counts on the top counter. Counters
+// sit kTicketStride bytes apart (17 x 256 B: another 256-byte channel slot and
+// 4 KB page each) so that the groups' atomics proceed in parallel instead of
+// queueing on one address.
+#ifndef RN_GROUPS_MAX
+#define RN_GROUPS_MAX 8
+#endif
+constexpr int kGroupsMax = RN_GROUPS_MAX;
+constexpr int kTicketStride = 17 * 256;
+inline size_t ticket_bytes(int groups) { return (size_t)(groups + 1) * kTicketStride; }
 constexpr int kBlock = 256;      // threads per workgroup of every kernel here
 constexpr int kWave = 64;
 
@@ -69,25 +80,31 @@ struct PassArgs {
     // lattice
     int nx, ny, nz, axis;
     int ntx, nty, ntz;           // tile counts
-    int tile_y, tile_z;          // rows per 2D strip / planes per 3D tile
+    int wrap;                    // bit k: direction k wraps around (periodic sides)
+    int tile_z;                  // planes per 3D tile
     int ntiles;                  // total workgroup tiles
-    int grid;                    // workgroups of this network per pass (multiple of 8)
+    int tpw;                     // tiles per workgroup, `grid` tiles apart (2D; 3D: 1)
+    int grid;                    // workgroups of this network per pass (multiple of 8 and of groups)
+    int groups;                  // completion-ticket groups (power of two, divides grid)
     // FP64 data
     const double *g64[3];        // original conductances
     double *P[2];                // full FP64 pressure field: CG passes after refresh m add their
                                  // step to P[m%2] in place; refresh m reads P[m%2], writes P[(m+1)%2]
     // inner-precision CG state
-    const T *gT[3];              // conductances in the inner precision (0 past the lattice edge)
+    const T *gT[3];              // conductances in the inner precision (0 past the lattice edge;
+                                 // the wrap bond on the last plane of a periodic direction)
     const T *invd;               // Jacobi preconditioner 1/d_i on live nodes, 0 elsewhere
     VecSet<T> src, dst;
     // reduction
     double *partials;            // [grid][kRed]
+    unsigned *tickets;           // groups + 1 counters, kTicketStride bytes apart, zero between passes
     Scalars *s;
 };
 
 struct Lat {
     int dim, axis, nx, ny, nz;
     int64_t n;
+    int wrap;    // bit k: direction k wraps around (periodic sides, extent >= 2)
 };
 
 // launchers (rn_kernels.hip)
@@ -105,10 +122,31 @@ template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
                        hipStream_t st);
 
-// tile geometry of the pass kernels: a 2D workgroup tile is 64 x 4 kTY2f
-// (FP32) or 64 x 4 kTY2d (FP64), kTY2f or kTY2d rows per wave; a 3D workgroup
-// tile is 64 x kTY x tile_z
-constexpr int kTX = 64, kTY = 16, kTY2f = 8, kTY2d = 4;
+// tile geometry of the pass kernels: a 2D workgroup tile is 64 kSEG2f x
+// 4 kTY2f (FP32) or 64 kSEG2d x 4 kTY2d (FP64): each wave holds kTY2f / kTY2d
+// rows of kSEG2f / kSEG2d 64-column segments; a 3D workgroup tile is
+// 64 x kTY x tile_z
+#ifndef RN_TY2F
+#define RN_TY2F 4
+#endif
+#ifndef RN_TY2D
+#define RN_TY2D 2
+#endif
+#ifndef RN_SEG2F
+#define RN_SEG2F 2
+#endif
+#ifndef RN_SEG2D
+#define RN_SEG2D 2
+#endif
+#ifndef RN_TY3
+#define RN_TY3 16
+#endif
+#ifndef RN_TZ3
+#define RN_TZ3 16
+#endif
+constexpr int kTX = 64, kTY = RN_TY3, kTZ = RN_TZ3;
+constexpr int kTY2f = RN_TY2F, kTY2d = RN_TY2D, kSEG2f = RN_SEG2F, kSEG2d = RN_SEG2D;
+
 
 __host__ __device__ inline int div_up(int a, int b) { return (a + b - 1) / b; }
 

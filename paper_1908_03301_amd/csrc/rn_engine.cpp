@@ -50,7 +50,7 @@ int check_shape(const rn_problem *p)
     const double n = (double)p->nx * (double)p->ny * (double)p->nz;
     if (n >= 2147483647.0) return RN_EINVAL;
     if (p->mem != RN_MEM_HOST && p->mem != RN_MEM_DEVICE) return RN_EINVAL;
-    if (p->reserved != 0) return RN_EINVAL;
+    if (p->flags & ~RN_PERIODIC) return RN_EINVAL;
     for (int k = 0; k < p->dim; ++k)
         if (!p->g[k]) return RN_EINVAL;
     if (p->dim == 2 && p->g[2]) return RN_EINVAL;
@@ -68,18 +68,35 @@ int check_opts(const rn_opts *o)
     return RN_OK;
 }
 
+int wrap_bits(const rn_problem *p)
+{
+    if (!(p->flags & RN_PERIODIC)) return 0;
+    const int64_t n[3] = {p->nx, p->ny, p->nz};
+    int bits = 0;
+    for (int k = 0; k < p->dim; ++k)
+        if (k != p->axis && n[k] >= 2) bits |= 1 << k;
+    return bits;
+}
+
+Lat make_lat(const rn_problem *p)
+{
+    return Lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, p->nx * p->ny * p->nz, wrap_bits(p)};
+}
+
 bool host_values_ok(const rn_problem *p)
 {
     const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
+    const int wrap = wrap_bits(p);
     for (int k = 0; k < p->dim; ++k) {
         const double *g = p->g[k];
+        const bool wk = (wrap >> k) & 1;   // the last plane's entries are wrap bonds
         for (int64_t z = 0; z < nz; ++z)
             for (int64_t y = 0; y < ny; ++y) {
                 const double *row = g + nx * (y + ny * z);
                 int64_t xe = nx;
-                if (k == 0) xe = nx - 1;
-                else if (k == 1 && y == ny - 1) xe = 0;
-                else if (k == 2 && z == nz - 1) xe = 0;
+                if (k == 0 && !wk) xe = nx - 1;
+                else if (k == 1 && y == ny - 1 && !wk) xe = 0;
+                else if (k == 2 && z == nz - 1 && !wk) xe = 0;
                 for (int64_t x = 0; x < xe; ++x) {
                     const double v = row[x];
                     if (!(v >= 0.0) || std::isinf(v)) return false;
@@ -98,6 +115,13 @@ double cross_section(const rn_problem *p)
     return s;
 }
 
+// A 2D workgroup runs two tiles per pass when the network has at least two
+// rounds of workgroups' worth of tiles (256 CUs x 4 workgroups = 1024 per
+// round): the per-workgroup tail (partials, ticket) is then paid once per two
+// tiles. Measured on the 2048^2 FP64 pass, three or four tiles per workgroup
+// were 2% slower than two.
+constexpr int kWGTarget2D = 1024, kTpwMax2D = 2;
+
 Layout make_layout(const rn_problem *p, const rn_opts *o)
 {
     Layout L;
@@ -106,20 +130,26 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.s = (o && o->precision == RN_MIXED) ? 4 : 8;
     L.copy_g = p->mem == RN_MEM_HOST;
     if (p->dim == 2) {
-        L.ntx = div_up((int)p->nx, kWave);
+        L.ntx = div_up((int)p->nx, kWave * (L.s == 4 ? kSEG2f : kSEG2d));
         L.nty = div_up((int)p->ny, (L.s == 4 ? kTY2f : kTY2d) * (kBlock / kWave));
         L.ntz = 1;
         L.ntiles = L.ntx * L.nty;
-        L.grid = L.ntiles;
+        L.tpw = std::max(1, std::min(kTpwMax2D, L.ntiles / kWGTarget2D));
+        L.grid = div_up(L.ntiles, L.tpw);
     } else {
-        L.tile_z = 16;
+        L.tile_z = kTZ;
         L.ntx = div_up((int)p->nx, kTX);
         L.nty = div_up((int)p->ny, kTY);
         L.ntz = div_up((int)p->nz, L.tile_z);
         L.ntiles = L.ntx * L.nty * L.ntz;
         L.grid = L.ntiles;
     }
-    L.grid = (L.grid + 7) / 8 * 8;
+    // completion-ticket groups: about one per 64 workgroups, a power of two
+    // up to kGroupsMax; the grid is a multiple of 8 (XCD remap) and of groups
+    L.groups = 1;
+    while (L.groups * 2 <= kGroupsMax && L.groups * 2 * 64 <= L.grid) L.groups *= 2;
+    const int gq = L.groups > 8 ? L.groups : 8;
+    L.grid = (L.grid + gq - 1) / gq * gq;
     const size_t n = (size_t)L.n;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -135,6 +165,7 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.off_invd = take((size_t)L.s * n);
     L.off_vec = take((size_t)6 * L.s * n);   // two sets of r, p, q; labels (8 bytes/node) alias here
     L.off_part = take((size_t)L.grid * kRed * 8);
+    L.off_tk = take(ticket_bytes(L.groups));
     L.off_cnt = take(4 * sizeof(unsigned long long));
     L.total = off;
     return L;
@@ -273,7 +304,7 @@ int Engine::prepare(Net *net, hipStream_t st, std::string *err)
     free_slots_.pop_back();
     by_slot_[net->slot] = net;
     net->na = p->axis == 0 ? p->nx : (p->axis == 1 ? p->ny : p->nz);
-    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
+    const Lat lat = make_lat(p);
     unsigned long long *cnt = (unsigned long long *)(base + L.off_cnt);
     if (!net->ev) ENG_TRY(hipEventCreateWithFlags(&net->ev, hipEventDisableTiming));
     for (hipEvent_t *e : {&net->ev_a, &net->ev_b, &net->ev_c, &net->ev_d})
@@ -289,6 +320,7 @@ int Engine::prepare(Net *net, hipStream_t st, std::string *err)
         for (int k = 0; k < p->dim; ++k) net->gd[k] = p->g[k];
     }
     ENG_TRY(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), st));
+    ENG_TRY(hipMemsetAsync(base + L.off_tk, 0, ticket_bytes(L.groups), st));
     if (!L.copy_g) ENG_TRY(launch_validate(lat, net->gd, cnt + 1, st));
     int *parent = (int *)(base + L.off_vec);
     unsigned *flags = (unsigned *)(base + L.off_vec + 4 * n);
@@ -322,10 +354,12 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.ntx = L.ntx;
         A.nty = L.nty;
         A.ntz = L.ntz;
-        A.tile_y = 0;
+        A.wrap = wrap_bits(p);
         A.tile_z = L.tile_z;
         A.ntiles = L.ntiles;
+        A.tpw = L.tpw;
         A.grid = L.grid;
+        A.groups = L.groups;
         for (int d = 0; d < 3; ++d) {
             A.g64[d] = net->gd[d];
             A.gT[d] = d < p->dim ? (const T *)(base + L.off_gT) + (size_t)d * n : nullptr;
@@ -336,6 +370,7 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.src = k == 0 ? s0 : s1;
         A.dst = k == 0 ? s1 : s0;
         A.partials = (double *)(base + L.off_part);
+        A.tickets = (unsigned *)(base + L.off_tk);
         A.s = ds;
         a2[(first_parity + k) & 1] = A;
     }
@@ -383,7 +418,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
         net->phase = NET_FINISHING;
         return RN_OK;
     }
-    Lat lat{p->dim, p->axis, (int)p->nx, (int)p->ny, (int)p->nz, L.n};
+    const Lat lat = make_lat(p);
     const int slot = net->slot;
     Scalars *ds = d_scal_ + slot;
     Scalars &init = h_init_[slot];

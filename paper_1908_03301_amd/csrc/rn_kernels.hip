@@ -154,12 +154,19 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
     s->check = 0;
 }
 
-// Per-workgroup partials, then the last workgroup to arrive reduces them in
-// block order (deterministic) and runs the scalar update.
-__device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, int lb, int grid, int mode)
+// Per-workgroup partials, then the last workgroup to arrive sums them in
+// block order (a fixed order, so the result does not depend on scheduling)
+// and runs the scalar update. Arrival is counted in two levels: on the counter
+// of the workgroup's group (lb mod groups), then, by the last of each group,
+// on the top counter. Device-scope atomics on one address are serviced one
+// after another, so a single counter for a 2048-workgroup pass queued 2048
+// atomics at the end of every pass.
+__device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tickets, Scalars *s, int lb, int grid,
+                            int groups, int mode)
 {
     __shared__ double red[kBlock / kWave][kRed];
     __shared__ int is_last;
+    constexpr int kStride = kTicketStride / (int)sizeof(unsigned);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
     for (int k = 0; k < kRed; ++k) {
@@ -174,11 +181,18 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, i
             st_through(&partials[(size_t)lb * kRed + k], v);
         }
         // wait until this thread's write-through stores have completed
-        // (s_waitcnt with every counter at 0), then take a ticket
-        // (device-scope atomic, coherent across XCDs)
+        // (s_waitcnt with every counter at 0), then count (device-scope
+        // atomics, coherent across XCDs); groups is a power of two dividing grid
         __builtin_amdgcn_s_waitcnt(0);
-        const unsigned prev = __hip_atomic_fetch_add(&s->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (prev == (unsigned)grid - 1u);
+        const unsigned prev = __hip_atomic_fetch_add(tickets + (lb & (groups - 1)) * kStride, 1u,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int last = prev == (unsigned)(grid / groups) - 1u;
+        if (last && groups > 1) {
+            const unsigned top = __hip_atomic_fetch_add(tickets + groups * kStride, 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            last = top == (unsigned)groups - 1u;
+        }
+        is_last = last;
     }
     __syncthreads();
     if (!is_last) return;
@@ -194,6 +208,9 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, i
         double v = wave_sum(tot[k]);
         if (lane == 0) red[w][k] = v;
     }
+    // every workgroup has counted: clear the counters for the next pass
+    if (threadIdx.x <= groups)
+        __hip_atomic_store(tickets + threadIdx.x * kStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (threadIdx.x == 0) {
         double t[kRed];
@@ -203,7 +220,6 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, Scalars *s, i
         }
         if (mode == MODE_CG) step_after_cg(s, t);
         else step_after_refresh(s, t);
-        s->ticket = 0u;
     }
 }
 
@@ -231,17 +247,21 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     const int64_t st[3] = {sx, sy, sz};
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        if (c[k] > 0) {
-            const double g = a.g64[k][i - st[k]];
+        const bool wk = (a.wrap >> k) & 1;       // never the flow axis
+        const int64_t span = (int64_t)(n[k] - 1) * st[k];
+        if (c[k] > 0 || wk) {
+            const int64_t j = c[k] > 0 ? i - st[k] : i + span;
+            const double g = a.g64[k][j];
             if (g != 0.0) {
-                r64 += g * (pn(i - st[k]) - pi);
+                r64 += g * (pn(j) - pi);
                 if (k == a.axis && c[k] == 1) qin += g * (1.0 - pi);
             }
         }
-        if (c[k] + 1 < n[k]) {
+        if (c[k] + 1 < n[k] || wk) {
+            const int64_t j = c[k] + 1 < n[k] ? i + st[k] : i - span;
             const double g = a.g64[k][i];
             if (g != 0.0) {
-                r64 += g * (pn(i + st[k]) - pi);
+                r64 += g * (pn(j) - pi);
                 if (k == a.axis && c[k] == n[k] - 2) qout += g * pi;
             }
         }
@@ -259,8 +279,9 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 }
 
 // ---------------------------------------------------------------- 2D pass
-// A workgroup owns a tile of 64 consecutive x and 4 TY rows; wave w holds rows
-// w TY .. w TY + TY - 1. Every load of the tile (the rows, one halo row above
+// A workgroup owns a tile of 64 SEG consecutive x and 4 TY rows; wave w holds
+// rows w TY .. w TY + TY - 1, each as SEG segments of 64 columns (lane l holds
+// columns x0 + 64 s + l). Every load of the tile (the rows, one halo row above
 // and below the workgroup, the halo columns, the bonds and the FP64
 // pressures) is issued up front at a clamped, in-bounds address with no
 // branch on loaded data, so the tile's whole memory traffic is in flight at
@@ -268,26 +289,49 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 // another wave's rows get that wave's p' through LDS (one barrier), so only 2
 // rows in 4 TY are re-read. Off the live set r = q = p = 0 in memory, so the
 // arithmetic needs no mask; only stores are restricted to the lattice.
-// x-neighbours come from lane shuffles; lanes 0..TY-1 and 64-TY..63 load the
-// halo columns x0-1 and x0+64 (one row each), which shuffles hand to lanes 0
-// and 63.
+// x-neighbours come from lane shuffles (across a segment junction from lane 63
+// of one segment and lane 0 of the next); lanes 0..TY-1 and 64-TY..63 load the
+// halo columns x0-1 and x0+64 SEG (one row each), which shuffles hand to lane
+// 0 of the first segment and lane 63 of the last.
 template <typename T>
 struct Tile2D {
-    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;   // rows per wave
-    static constexpr int ROWS = TY * (kBlock / kWave);         // rows per workgroup
+    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;     // rows per wave
+    static constexpr int SEG = sizeof(T) == 4 ? kSEG2f : kSEG2d;  // 64-column segments per row
+    static constexpr int ROWS = TY * (kBlock / kWave);           // rows per workgroup
+    static constexpr int COLS = kWave * SEG;                     // columns per workgroup
 };
 
 template <typename T>
-__device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x, int yb, int lane,
+__device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int yb, int lane,
                                           int w, T alpha, T beta, double sa, double (&acc)[kRed])
 {
     constexpr int TY = Tile2D<T>::TY;
+    constexpr int SEG = Tile2D<T>::SEG;
     constexpr int NW = kBlock / kWave;
-    __shared__ T edge[2][NW][kWave];   // [0]: first row of each wave, [1]: last row
+    __shared__ T edge[2][NW][SEG][kWave];   // [0]: first row of each wave, [1]: last row
     const int nx = a.nx, ny = a.ny;
     const int y0 = yb + w * TY;        // first row of this wave
-    const bool valid = x < nx;
-    const int xc = valid ? x : nx - 1;
+    // Plane a lane or row slot holds: its own inside the lattice; across a
+    // periodic direction the plane just past either edge holds the image of
+    // the opposite edge (x = nx is column 0, y = -1 is row ny - 1), so the
+    // stencil reads the wrapped neighbours like any other; -1 = none.
+    const bool wx = a.wrap & 1, wy = (a.wrap >> 1) & 1;
+    auto colm = [&](int xx) { return xx >= 0 && xx < nx ? xx : (wx && xx == nx ? 0 : (wx && xx == -1 ? nx - 1 : -1)); };
+    auto rowm = [&](int yy) { return yy >= 0 && yy < ny ? yy : (wy && yy == ny ? 0 : (wy && yy == -1 ? ny - 1 : -1)); };
+    auto rowc = [&](int yy) {          // row to load for slot yy (clamped where it holds none)
+        const int m = rowm(yy);
+        return m >= 0 ? m : (yy < 0 ? 0 : ny - 1);
+    };
+    bool valid[SEG], lv[SEG];          // a lattice node (stored, reduced) / holds a column or an image
+    int xc[SEG];
+#pragma unroll
+    for (int sg = 0; sg < SEG; ++sg) {
+        const int x = x0 + kWave * sg + lane;
+        const int xm = colm(x);
+        valid[sg] = x < nx;
+        lv[sg] = xm >= 0;
+        xc[sg] = lv[sg] ? xm : nx - 1;
+    }
     const T *__restrict__ rs = a.src.r;
     const T *__restrict__ qs = a.src.q;
     const T *__restrict__ ps = a.src.p;
@@ -297,44 +341,60 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     T *__restrict__ pd = a.dst.p;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
-    auto rowc = [&](int yy) { return yy < 0 ? 0 : (yy >= ny ? ny - 1 : yy); };
 
     // ---- issue every load
-    T d_[TY], r_[TY], q_[TY], p_[TY];
-    double Pv[TY];
-    T gxv[TY], gyv[TY + 1];
+    T d_[SEG][TY], r_[SEG][TY], q_[SEG][TY], p_[SEG][TY];
+    double Pv[SEG][TY];
+    T gxv[SEG][TY], gyv[SEG][TY + 1];
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
-        const int64_t i = (int64_t)rowc(y0 + j) * nx + xc;
-        d_[j] = dv[i];
-        r_[j] = rs[i];
-        q_[j] = qs[i];
-        p_[j] = ps[i];
-        Pv[j] = P[i];
-        gxv[j] = gx[i];
-        gyv[j + 1] = gy[i];
-    }
-    gyv[0] = y0 >= 1 ? gy[(int64_t)rowc(y0 - 1) * nx + xc] : T(0);   // bond below the wave (none at y = 0)
-    // the workgroup's outer halo rows: wave 0 the row above, the last wave the row below
-    T ed = T(0), er = T(0), eq = T(0), ep = T(0);
-    if (w == 0 || w == NW - 1) {   // wave-uniform
-        const int yh = w == 0 ? yb - 1 : yb + NW * TY;
-        const bool hrow = valid && yh >= 0 && yh < ny;
-        const int64_t i = (int64_t)rowc(yh) * nx + xc;
-        const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i];
-        if (hrow) {
-            ed = d0;
-            er = r0;
-            eq = q0;
-            ep = p0;
+        const int64_t ro = (int64_t)rowc(y0 + j) * nx;
+#pragma unroll
+        for (int sg = 0; sg < SEG; ++sg) {
+            const int64_t i = ro + xc[sg];
+            d_[sg][j] = dv[i];
+            r_[sg][j] = rs[i];
+            q_[sg][j] = qs[i];
+            p_[sg][j] = ps[i];
+            Pv[sg][j] = P[i];
+            gxv[sg][j] = gx[i];
+            gyv[sg][j + 1] = gy[i];
         }
     }
-    // halo columns: lane l < TY holds (x0-1, y0+l), lane 64-TY+l holds (x0+64, y0+l)
+    {   // bond below the wave: none at y = 0 unless y wraps (then the bond ny-1 -> 0)
+        const bool below = rowm(y0 - 1) >= 0;
+        const int64_t ro = (int64_t)rowc(y0 - 1) * nx;
+#pragma unroll
+        for (int sg = 0; sg < SEG; ++sg) {
+            const T g0 = gy[ro + xc[sg]];
+            gyv[sg][0] = below ? g0 : T(0);
+        }
+    }
+    // the workgroup's outer halo rows: wave 0 the row above, the last wave the row below
+    T ed[SEG], er[SEG], eq[SEG], ep[SEG];
+#pragma unroll
+    for (int sg = 0; sg < SEG; ++sg) ed[sg] = er[sg] = eq[sg] = ep[sg] = T(0);
+    if (w == 0 || w == NW - 1) {   // wave-uniform
+        const int yh = w == 0 ? yb - 1 : yb + NW * TY;
+        const bool hrow = rowm(yh) >= 0;
+        const int64_t ro = (int64_t)rowc(yh) * nx;
+#pragma unroll
+        for (int sg = 0; sg < SEG; ++sg) {
+            const int64_t i = ro + xc[sg];
+            const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i];
+            if (hrow && lv[sg]) {
+                ed[sg] = d0;
+                er[sg] = r0;
+                eq[sg] = q0;
+                ep[sg] = p0;
+            }
+        }
+    }
+    // halo columns: lane l < TY holds (x0-1, y0+l), lane 64-TY+l holds (x0+64 SEG, y0+l)
     const bool hleft = lane < TY, hright = lane >= kWave - TY;
     const int hr_ = hleft ? lane : lane - (kWave - TY);
-    const int x0 = x - lane;
-    const int hx = hleft ? x0 - 1 : x0 + kWave;
-    const bool hok = (hleft || hright) && hx >= 0 && hx < nx && y0 + hr_ < ny;
+    const int hx = colm(hleft ? x0 - 1 : x0 + Tile2D<T>::COLS);
+    const bool hok = (hleft || hright) && hx >= 0 && y0 + hr_ < ny;
     T hd = T(0), hr = T(0), hq = T(0), hp = T(0), hg = T(0);
     {
         const int64_t i = hok ? (int64_t)(y0 + hr_) * nx + hx : 0;
@@ -344,64 +404,83 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             hr = r0;
             hq = q0;
             hp = p0;
-            hg = hleft ? g0 : T(0);        // bond (x0-1) -> x0 for lane 0
+            hg = hleft ? g0 : T(0);        // bond (x0-1) -> x0 for lane 0 (nx-1 -> 0 when x wraps)
         }
     }
 
     // ---- p' on the wave's rows, exchanged with the neighbouring waves
-    T pv[TY + 2];   // rows y0-1 .. y0+TY
+    T pv[SEG][TY + 2];   // rows y0-1 .. y0+TY
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
-        const bool ok = valid && y0 + j < ny;
-        const T v = d_[j] * (r_[j] - alpha * q_[j]) + beta * p_[j];
-        pv[j + 1] = ok ? v : T(0);
+        const bool rheld = rowm(y0 + j) >= 0;
+#pragma unroll
+        for (int sg = 0; sg < SEG; ++sg) {
+            const T v = d_[sg][j] * (r_[sg][j] - alpha * q_[sg][j]) + beta * p_[sg][j];
+            pv[sg][j + 1] = (rheld && lv[sg]) ? v : T(0);
+        }
     }
-    edge[0][w][lane] = pv[1];
-    edge[1][w][lane] = pv[TY];
-    const T hv = ed * (er - alpha * eq) + beta * ep;     // zero unless hrow
+#pragma unroll
+    for (int sg = 0; sg < SEG; ++sg) {
+        edge[0][w][sg][lane] = pv[sg][1];
+        edge[1][w][sg][lane] = pv[sg][TY];
+    }
+    T hv[SEG];
+#pragma unroll
+    for (int sg = 0; sg < SEG; ++sg) hv[sg] = ed[sg] * (er[sg] - alpha * eq[sg]) + beta * ep[sg];   // zero unless held
     __syncthreads();
-    pv[0] = w == 0 ? hv : edge[1][w - 1][lane];
-    pv[TY + 1] = w == NW - 1 ? hv : edge[0][w + 1][lane];
+#pragma unroll
+    for (int sg = 0; sg < SEG; ++sg) {
+        pv[sg][0] = w == 0 ? hv[sg] : edge[1][w - 1][sg][lane];
+        pv[sg][TY + 1] = w == NW - 1 ? hv[sg] : edge[0][w + 1][sg][lane];
+    }
     const T hpv = hd * (hr - alpha * hq) + beta * hp;    // zero when !hok
 
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
         const int yy = y0 + j;
-        const bool ok = valid && yy < ny;
-        const T dc = ok ? d_[j] : T(0);
-        const T rc = ok ? r_[j] - alpha * q_[j] : T(0);
-        const T pc = pv[j + 1];
-        // neighbours across x
-        T pl = __shfl_up(pc, 1, kWave);
-        T pr = __shfl_down(pc, 1, kWave);
-        T gxl = __shfl_up(gxv[j], 1, kWave);
         const T hl = __shfl(hpv, j, kWave);
         const T hrr = __shfl(hpv, kWave - TY + j, kWave);
         const T hgl = __shfl(hg, j, kWave);
-        if (lane == 0) {
-            pl = hl;
-            gxl = hgl;
+#pragma unroll
+        for (int sg = 0; sg < SEG; ++sg) {
+            const bool ok = valid[sg] && yy < ny;
+            const T dc = ok ? d_[sg][j] : T(0);
+            const T rc = ok ? r_[sg][j] - alpha * q_[sg][j] : T(0);
+            const T pc = pv[sg][j + 1];
+            // neighbours across x: shuffles inside a segment, the neighbouring
+            // segment's edge lane across a junction, the halo at the tile edges
+            T pl = __shfl_up(pc, 1, kWave);
+            T pr = __shfl_down(pc, 1, kWave);
+            T gxl = __shfl_up(gxv[sg][j], 1, kWave);
+            const T lj = sg == 0 ? hl : __shfl(pv[sg > 0 ? sg - 1 : 0][j + 1], kWave - 1, kWave);
+            const T gj = sg == 0 ? hgl : __shfl(gxv[sg > 0 ? sg - 1 : 0][j], kWave - 1, kWave);
+            const T rj = sg == SEG - 1 ? hrr : __shfl(pv[sg < SEG - 1 ? sg + 1 : 0][j + 1], 0, kWave);
+            if (lane == 0) {
+                pl = lj;
+                gxl = gj;
+            }
+            if (lane == kWave - 1) pr = rj;
+            T qv = gxl * (pc - pl) + gxv[sg][j] * (pc - pr) + gyv[sg][j] * (pc - pv[sg][j]) +
+                   gyv[sg][j + 1] * (pc - pv[sg][j + 2]);
+            if (dc == T(0)) qv = T(0);
+            // every in-lattice node is stored (zeros and unchanged pressures off the
+            // live set) so that cache lines are written whole
+            if (ok) {
+                const int64_t i = (int64_t)yy * nx + x0 + kWave * sg + lane;
+                P[i] = Pv[sg][j] + sa * (double)p_[sg][j];
+                rd[i] = rc;
+                pd[i] = pc;
+                qd[i] = qv;
+            }
+            const double dq = (double)qv;
+            const double dp = (double)pc, dr = (double)rc;
+            const double dd = (double)dc, dz = dd * dr;
+            acc[0] += dp * dq;
+            acc[1] += dz * dq;
+            acc[2] += dq * dq * dd;
+            acc[3] += dr * dz;
+            acc[4] += dr * dr;
         }
-        if (lane == kWave - 1) pr = hrr;
-        T qv = gxl * (pc - pl) + gxv[j] * (pc - pr) + gyv[j] * (pc - pv[j]) + gyv[j + 1] * (pc - pv[j + 2]);
-        if (dc == T(0)) qv = T(0);
-        // every in-lattice node is stored (zeros and unchanged pressures off the
-        // live set) so that cache lines are written whole
-        if (ok) {
-            const int64_t i = (int64_t)yy * nx + x;
-            P[i] = Pv[j] + sa * (double)p_[j];
-            rd[i] = rc;
-            pd[i] = pc;
-            qd[i] = qv;
-        }
-        const double dq = (double)qv;
-        const double dp = (double)pc, dr = (double)rc;
-        const double dd = (double)dc, dz = dd * dr;
-        acc[0] += dp * dq;
-        acc[1] += dz * dq;
-        acc[2] += dq * dq * dd;
-        acc[3] += dr * dz;
-        acc[4] += dr * dr;
     }
 }
 
@@ -422,24 +501,32 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
     if (mode == MODE_DONE) return;
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int tile = xcd_remap(lb, a.grid);      // uniform per workgroup
+    const int first = xcd_remap(lb, a.grid);     // uniform per workgroup
     const int m = (int)(s->refreshes & 1);
     const double sa = s->sigma * s->alpha;
-    if (tile < a.ntiles) {
+    // a workgroup takes a.tpw tiles, grid apart (each XCD keeps contiguous ranges)
+    for (int k = 0; k < a.tpw; ++k) {
+        const int tile = first + k * a.grid;
+        if (tile >= a.ntiles) break;
+        if (k > 0) __syncthreads();              // the previous tile's LDS rows are reused
         const int tx = tile % a.ntx, ty = tile / a.ntx;
-        const int x = tx * kWave + lane;
+        const int x0 = tx * Tile2D<T>::COLS;
         const int yb = ty * Tile2D<T>::ROWS;
         if (mode == MODE_CG) {
-            cg2d_tile<T>(a, a.P[m], x, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
-        } else if (x < a.nx) {
+            cg2d_tile<T>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
+        } else {
             const double sigma_next = s->sigma_next;
             const int y0 = yb + w * Tile2D<T>::TY;
             const int y1 = min(y0 + Tile2D<T>::TY, a.ny);
-            for (int yy = y0; yy < y1; ++yy)
-                refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
+            for (int sg = 0; sg < Tile2D<T>::SEG; ++sg) {
+                const int x = x0 + kWave * sg + lane;
+                if (x < a.nx)
+                    for (int yy = y0; yy < y1; ++yy)
+                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
+            }
         }
     }
-    finish_pass(acc, a.partials, s, lb, a.grid, mode);
+    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
 }
 
 // ---------------------------------------------------------------- 3D pass
@@ -479,8 +566,18 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int x = x0 + lane;
-    const bool xok = x < nx;
-    const int xc = xok ? x : nx - 1;
+    // Plane a lane, row slot or z step holds: its own inside the lattice;
+    // across a periodic direction the plane just past either edge holds the
+    // image of the opposite edge, so wrapped neighbours are read like any
+    // other; -1 = none.
+    const bool wx = a.wrap & 1, wy = (a.wrap >> 1) & 1, wz = (a.wrap >> 2) & 1;
+    auto colm = [&](int v) { return v >= 0 && v < nx ? v : (wx && v == nx ? 0 : (wx && v == -1 ? nx - 1 : -1)); };
+    auto rowm = [&](int v) { return v >= 0 && v < ny ? v : (wy && v == ny ? 0 : (wy && v == -1 ? ny - 1 : -1)); };
+    auto plm = [&](int v) { return v >= 0 && v < nz ? v : (wz && v == nz ? 0 : (wz && v == -1 ? nz - 1 : -1)); };
+    const bool xok = x < nx;           // a lattice node: stored and reduced
+    const int xm = colm(x);
+    const bool xl = xm >= 0;           // holds a column (its own or an image)
+    const int xc = xl ? xm : nx - 1;
     const T *__restrict__ rs = a.src.r;
     const T *__restrict__ qs = a.src.q;
     const T *__restrict__ ps = a.src.p;
@@ -492,13 +589,15 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ gy = a.gT[1];
     const T *__restrict__ gz = a.gT[2];
     const int yw = y0 + w * kRows;                 // first row of this wave
-    bool rok[kRows];
+    bool rok[kRows], lok[kRows];                   // lattice node / slot holding a node or an image
     int64_t rowoff[kRows];                         // clamped x + sy * y of each row
 #pragma unroll
     for (int j = 0; j < kRows; ++j) {
         const int yy = yw + j;
+        const int ym = rowm(yy);
         rok[j] = xok && yy < ny;
-        rowoff[j] = xc + sy * (yy < ny ? yy : ny - 1);
+        lok[j] = xl && ym >= 0;
+        rowoff[j] = xc + sy * (ym >= 0 ? ym : ny - 1);
     }
     // halo ring: wave 0 row y0-1, wave 1 row y0+16, wave 2 lanes 0..15 column
     // x0-1 and lanes 16..31 column x0+64 (rows y0..y0+15)
@@ -508,15 +607,21 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     else if (w == 2 && lane < kTY) { hx = x0 - 1; hy = y0 + lane; hrow = 1 + lane; hcol = 0; }
     else if (w == 2 && lane < 2 * kTY) { hx = x0 + kTX; hy = y0 + lane - kTY; hrow = 1 + lane - kTY; hcol = kTX + 1; }
     else { hx = -1; hy = -1; hrow = -1; hcol = 0; }
-    const bool hok = hx >= 0 && hx < nx && hy >= 0 && hy < ny;
-    const int64_t hoff = hok ? hx + sy * hy : 0;
-    // bond halos: lane j < kRows holds gx at (x0-1, yw+j); every lane holds gy at (x, yw-1)
-    const bool xhok = lane < kRows && x0 >= 1 && yw + lane < ny;
-    const int64_t xhoff = xhok ? (x0 - 1) + sy * (yw + lane) : 0;
-    const bool yhok = xok && yw >= 1 && yw - 1 < ny;
-    const int64_t yhoff = yhok ? xc + sy * (yw - 1) : 0;
+    const int hxm = hrow >= 0 ? colm(hx) : -1, hym = hrow >= 0 ? rowm(hy) : -1;
+    const bool hok = hxm >= 0 && hym >= 0;
+    const int64_t hoff = hok ? hxm + sy * hym : 0;
+    // bond halos: lane j < kRows holds gx at (x0-1, yw+j); every lane holds gy
+    // at (x, yw-1) (on a periodic direction the wrap bond at the first plane)
+    const int xbm = colm(x0 - 1), ybm = rowm(yw - 1);
+    const bool xhok = lane < kRows && xbm >= 0 && yw + lane < ny;
+    const int64_t xhoff = xhok ? xbm + sy * (yw + lane) : 0;
+    const bool yhok = xl && ybm >= 0;
+    const int64_t yhoff = yhok ? xc + sy * ybm : 0;
 
-    auto zc_ = [&](int zz) { return (int64_t)(zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz)) * sz; };
+    auto zc_ = [&](int zz) {
+        const int m = plm(zz);
+        return (int64_t)(m >= 0 ? m : (zz < 0 ? 0 : nz - 1)) * sz;
+    };
     auto load_raw = [&](Raw3<T> &R, int zz, bool ring) {
         const int64_t zo = zc_(zz);
 #pragma unroll
@@ -560,10 +665,10 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 
     // ---- prologue: plane z0-1 (own rows), plane z0 (rows, ring, LDS), bonds of z0
     {
-        const bool in = z0 - 1 >= 0;
+        const bool in = plm(z0 - 1) >= 0;
         load_raw(R, z0 - 1, false);
 #pragma unroll
-        for (int j = 0; j < kRows; ++j) pm[j] = (in && rok[j]) ? pprime(R.d[j], R.r[j], R.q[j], R.p[j]) : T(0);
+        for (int j = 0; j < kRows; ++j) pm[j] = (in && lok[j]) ? pprime(R.d[j], R.r[j], R.q[j], R.p[j]) : T(0);
         load_raw(R, z0, true);
         load_bonds(Gc, z0);
 #pragma unroll
@@ -572,7 +677,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         for (int j = 0; j < kRows; ++j) {
             const bool ok = rok[j];
             const T r_ = R.r[j] - alpha * R.q[j];
-            pc[j] = ok ? R.d[j] * r_ + beta * R.p[j] : T(0);
+            pc[j] = lok[j] ? R.d[j] * r_ + beta * R.p[j] : T(0);
             rc[j] = ok ? r_ : T(0);
             dc[j] = ok ? R.d[j] : T(0);
             if (ok) {
@@ -590,12 +695,13 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         const int zn = zc + 1;
         const bool nin = zn < z1;                // plane zc+1 belongs to this block
         const bool nlat = zn < nz;               // plane zc+1 is inside the lattice
+        const bool nheld = plm(zn) >= 0;         // ... or is the image of plane 0
         // (a) plane zc+1 from the loads issued one iteration ago
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const bool ok = rok[j] && nlat;
             const T r_ = R.r[j] - alpha * R.q[j];
-            pn[j] = ok ? R.d[j] * r_ + beta * R.p[j] : T(0);
+            pn[j] = (lok[j] && nheld) ? R.d[j] * r_ + beta * R.p[j] : T(0);
             rn[j] = ok ? r_ : T(0);
             dn[j] = ok ? R.d[j] : T(0);
             if (ok && nin) {
@@ -686,7 +792,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
                 }
         }
     }
-    finish_pass(acc, a.partials, s, lb, a.grid, mode);
+    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
 }
 
 // ---------------------------------------------------------------- setup kernels
@@ -706,7 +812,7 @@ __device__ __forceinline__ int face_code(const Lat &L, int x, int y, int z)
     return c == 0 ? 1 : (c == na - 1 ? 2 : 0);
 }
 
-// Count in-lattice conductances that are negative, NaN or infinite.
+// Count lattice conductances (wrap bonds included) that are negative, NaN or infinite.
 __global__ void validate_kernel(Lat L, const double *g0, const double *g1, const double *g2,
                                 unsigned long long *bad)
 {
@@ -719,7 +825,7 @@ __global__ void validate_kernel(Lat L, const double *g0, const double *g1, const
         const int c[3] = {x, y, z};
         const int n[3] = {L.nx, L.ny, L.nz};
         for (int k = 0; k < L.dim; ++k) {
-            if (c[k] + 1 >= n[k]) continue;
+            if (c[k] + 1 >= n[k] && !((L.wrap >> k) & 1)) continue;   // ignored edge entry
             const double v = g[k][i];
             if (!(v >= 0.0) || isinf(v)) ++cnt;
         }
@@ -772,7 +878,8 @@ __global__ void uf_init_kernel(int64_t n, int *parent, unsigned *flags)
     }
 }
 
-// Union across every occupied bond joining two interior nodes.
+// Union across every occupied bond joining two interior nodes (a wrap bond
+// joins two nodes of the same plane along the flow axis).
 __global__ void uf_union_kernel(Lat L, const double *g0, const double *g1, const double *g2, int *parent)
 {
     const double *g[3] = {g0, g1, g2};
@@ -785,9 +892,13 @@ __global__ void uf_union_kernel(Lat L, const double *g0, const double *g1, const
         const int c[3] = {x, y, z};
         const int n[3] = {L.nx, L.ny, L.nz};
         for (int k = 0; k < L.dim; ++k) {
-            if (c[k] + 1 >= n[k] || !(g[k][i] > 0.0)) continue;
+            int64_t j;
+            if (c[k] + 1 < n[k]) j = i + st[k];
+            else if ((L.wrap >> k) & 1) j = i - (int64_t)(n[k] - 1) * st[k];   // wrap bond (never the flow axis)
+            else continue;
+            if (!(g[k][i] > 0.0)) continue;
             if (k == L.axis && c[k] + 1 == n[k] - 1) continue;     // neighbour on the outlet face
-            uf_union(parent, (int)i, (int)(i + st[k]));
+            uf_union(parent, (int)i, (int)j);
         }
     }
 }
@@ -842,8 +953,10 @@ __global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, con
                 const int n[3] = {L.nx, L.ny, L.nz};
                 double d = 0.0;
                 for (int k = 0; k < L.dim; ++k) {
+                    const bool wk = (L.wrap >> k) & 1;
                     if (c[k] > 0) d += g[k][i - st[k]];
-                    if (c[k] + 1 < n[k]) d += g[k][i];
+                    else if (wk) d += g[k][i + (int64_t)(n[k] - 1) * st[k]];
+                    if (c[k] + 1 < n[k] || wk) d += g[k][i];
                 }
                 s = d;
                 ++cnt;
@@ -870,7 +983,7 @@ __global__ void scale_kernel(Lat L, const double *g0, const double *g1, const do
         coords(L, i, x, y, z);
         const int c[3] = {x, y, z};
         const int n[3] = {L.nx, L.ny, L.nz};
-        for (int k = 0; k < L.dim; ++k) h[k][i] = (c[k] + 1 < n[k]) ? (T)g[k][i] : T(0);
+        for (int k = 0; k < L.dim; ++k) h[k][i] = (c[k] + 1 < n[k] || ((L.wrap >> k) & 1)) ? (T)g[k][i] : T(0);
         const double d = dlive[i];
         invd[i] = d > 0.0 ? (T)(1.0 / d) : T(0);
     }

@@ -51,9 +51,9 @@ struct Layout {
     int64_t n = 0;
     int dim = 2, s = 8;
     bool copy_g = false;
-    int grid = 8, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_z = 16;
+    int grid = 8, groups = 1, tpw = 1, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_z = 16;
     size_t off_g64 = 0, off_P = 0, off_dl = 0, off_mask = 0, off_gT = 0, off_invd = 0, off_vec = 0,
-           off_part = 0, off_cnt = 0, total = 0;
+           off_part = 0, off_tk = 0, off_cnt = 0, total = 0;
 };
 Layout make_layout(const rn_problem *p, const rn_opts *o);
 
@@ -178,6 +178,8 @@ namespace rn {
 int check_shape(const rn_problem *p);
 int check_opts(const rn_opts *o);
 bool host_values_ok(const rn_problem *p);
+int wrap_bits(const rn_problem *p);   // bit k: direction k is periodic
+Lat make_lat(const rn_problem *p);
 double cross_section(const rn_problem *p);
 double now_s();
 }  // namespace rn

@@ -73,7 +73,8 @@ def test_validate_rejects_bad_arguments(lib):
     assert B.rn_validate(_prob(axis=2)) == B.RN_EINVAL
     assert B.rn_validate(_prob(nx=0)) == B.RN_EINVAL
     assert B.rn_validate(_prob(mem=7)) == B.RN_EINVAL
-    assert B.rn_validate(_prob(reserved=1)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(flags=2)) == B.RN_EINVAL
+    assert B.rn_validate(_prob(flags=B.RN_PERIODIC)) == B.RN_OK
     p = _prob()
     p.c.g[1] = None
     assert B.rn_validate(p) == B.RN_EINVAL
@@ -98,6 +99,15 @@ def test_validate_rejects_bad_conductance(lib, bad):
     g[2][-1, 2, 3] = bad
     g[0][1, 1, -1] = bad
     assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 0))) == B.RN_OK
+    # with periodic sides the last-plane entries of the directions other than
+    # the flow axis are wrap bonds and are checked; along the flow axis they
+    # stay ignored
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 0), periodic=True)) == B.RN_EINVAL
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 1), periodic=True)) == B.RN_EINVAL
+    g = [a.copy() for a in net.g]
+    g[0][1, 1, -1] = bad
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 0), periodic=True)) == B.RN_OK
+    assert B.rn_validate(B.problem(I.Network(3, 5, 4, 3, g, 1), periodic=True)) == B.RN_EINVAL
 
 
 def test_footprint(lib):

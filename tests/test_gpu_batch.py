@@ -24,7 +24,7 @@ def say(msg):
 
 
 def mixed_set():
-    """Uneven networks: 2D and 3D, both precisions, ragged shapes, all axes."""
+    """Uneven networks: 2D and 3D, both precisions, ragged shapes, all axes, both side conditions."""
     nets = [
         (I.fbm_network(2, 200, 150, 1, H=0.7, sigma=1.5, occupancy=0.6, index=700), B.RN_FP64, 1e-10),
         (I.fbm_network(2, 129, 257, 1, H=0.35, sigma=1.5, occupancy=0.55, index=701).with_axis(1), B.RN_MIXED, 1e-8),
@@ -36,6 +36,10 @@ def mixed_set():
         (I.stratified_network(24, H=0.8, sigma=2.0, occupancy=0.4, index=705).with_axis(2), B.RN_MIXED, 1e-8),
         (I.fbm_network(2, 300, 5, 1, H=0.7, sigma=1.5, occupancy=0.9, index=706), B.RN_FP64, 1e-10),
         (I.fbm_network(3, 5, 70, 18, H=0.7, sigma=1.0, occupancy=0.7, index=707).with_axis(1), B.RN_MIXED, 1e-8),
+        # periodic sides (each network carries its own flag through the batch)
+        (I.fbm_network(2, 130, 70, 1, H=0.7, sigma=1.5, occupancy=0.7, index=708, periodic=True).with_axis(1),
+         B.RN_MIXED, 1e-8),
+        (I.fbm_network(3, 40, 33, 17, H=0.7, sigma=1.0, occupancy=0.6, index=709, periodic=True), B.RN_FP64, 1e-10),
     ]
     return nets
 

@@ -255,6 +255,25 @@ def test_full_2048_fbm(ctx, oracle_mod):
         say(f"K axis {axis} = {res.K!r} iters {res.iters} loop {res.t_loop_s:.3f}s")
 
 
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_large_ragged_several_tiles_per_workgroup(ctx, oracle_mod, precision):
+    """1900 x 2000 FBM: 3,750 (FP64) or 1,875 (FP32) tiles, so workgroups run
+    2 (FP64) or 1 (FP32) tiles per pass, over a grid that does not divide the
+    tile count in FP64; checked with the oracle's mask and operator."""
+    net = I.fbm_network(2, 1900, 2000, 1, H=0.7, sigma=1.5, occupancy=0.65, index=31)
+    for axis in (0, 1):
+        n2 = net.with_axis(axis)
+        res, P, M = gpu_solve(ctx, n2, precision)
+        ref_mask, nl = oracle_mod.mask_bfs(n2)
+        np.testing.assert_array_equal(M, ref_mask)
+        assert res.n_live == nl
+        assert res.converged and res.rel_resid <= SOLVE_TOL[precision]
+        c = oracle_mod.check_pressure(n2, P)
+        assert c.rel_resid <= 1.01 * SOLVE_TOL[precision]
+        assert res.G == pytest.approx(c.G_E, rel=1e-9)
+        assert c.p_min >= -1e-12 and c.p_max <= 1 + 1e-12
+
+
 def test_full_2048_duality(ctx):
     """Planar duality at 2048^2 (undiluted FBM): G(primal) G(dual, 1/g) = 1."""
     net = I.fbm_network(2, 2048, 2048, 1, H=0.7, sigma=1.5, occupancy=1.0, index=0)
