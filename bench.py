@@ -44,6 +44,9 @@ MULTI = {
     "serve": "served request stream, Poisson arrivals at 0.7 x the measured batched saturation rate; nodes "
              "log-uniform in [1e4, 3e7], 2D/3D 50/50, FBM ln g (H=0.75, sigma=1.5), occupancy U(0.3,1), "
              "flow along x; requests cycle through a pre-generated seeded pool",
+    "aniso": "permeability anisotropy study (Eq. 2, Fig. 10): 2D 512x512 FBM ln g (sigma=1.5) with "
+             "beta_x/beta_y in {1,2,4,8,16} and H in {0.75,0.35}, 16 networks each, K_x and K_y of every "
+             "network in one batch",
 }
 
 
@@ -154,7 +157,8 @@ def main():
         return
 
     if args.workload in MULTI:
-        out = batch_bench(args, B, I, np) if args.workload == "batch512" else serve_bench(args, B, I, np)
+        run = {"batch512": batch_bench, "serve": serve_bench, "aniso": aniso_bench}[args.workload]
+        out = run(args, B, I, np)
         print(json.dumps(out), flush=True)
         return
 
@@ -235,6 +239,11 @@ def main():
 def _gen_batch(spec):
     from paper_1908_03301_amd import inputs as I
     return I.batch_network(spec)
+
+
+def _gen_aniso(spec):
+    from paper_1908_03301_amd import inputs as I
+    return I.aniso_network(spec)
 
 
 def _gen_stream(req):
@@ -325,6 +334,44 @@ def batch_bench(args, B, I, np):
     out["mixed_batched_vs_fp64_one_at_a_time"] = round(value / out["fp64_cg_one_at_a_time_solves_per_s"], 3)
     out["max_K_rel_diff_mixed_vs_fp64"] = float(max(abs(a.K / b.K - 1.0) for a, b in zip(res_m, res_d) if b.K > 0))
     ctx.close()
+    return out
+
+
+def aniso_bench(args, B, I, np):
+    """K_x / K_y of anisotropic FBM networks (Eq. 2): both axes of every network
+    in one rn_solve_batch, mixed precision to tol; the ratio's range per
+    (H, beta_x / beta_y) is the quantity of Fig. 10."""
+    import torch
+    specs = I.aniso_specs()
+    nets = generate(_gen_aniso, specs, "aniso")
+    gd = [[torch.from_numpy(a).to("cuda") for a in n.g] for n in nets]
+    torch.cuda.synchronize()
+    probs = [B.problem(dim=2, nx=n.nx, ny=n.ny, nz=1, axis=ax, g=g) for n, g in zip(nets, gd) for ax in (0, 1)]
+    ctx = B.Context(0)
+    walls, res = [], None
+    for it in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = ctx.solve_batch(probs, B.opts(B.RN_MIXED, args.tol))
+        w = time.perf_counter() - t
+        print(f"[bench] aniso {'warmup' if it < args.warmup else 'step'} {it}: {w:.3f}s", file=sys.stderr, flush=True)
+        if any(r.status != 0 or not r.converged for r in res):
+            raise SystemExit("aniso batch member failed")
+        if it >= args.warmup:
+            walls.append(w)
+    ctx.close()
+    value = len(probs) * len(walls) / sum(walls)
+    table = {}
+    for k, sp in enumerate(specs):
+        kx, ky = res[2 * k].K, res[2 * k + 1].K
+        table.setdefault(f"H={sp.H:g} beta_x/beta_y={sp.ratio:g}", []).append(kx / ky if ky > 0 else float("inf"))
+    summary = {key: {"min": round(min(v), 3), "median": round(float(np.median(v)), 3), "max": round(max(v), 3),
+                     "networks": len(v)} for key, v in table.items()}
+    out = _contract(args, value, "solves/s", sum(walls), len(walls),
+                    {"workload": MULTI["aniso"], "networks": len(nets), "solves": len(probs),
+                     "nodes": sum(n.n for n in nets), "tol": args.tol,
+                     "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"})
+    out["Kx_over_Ky"] = summary
     return out
 
 

@@ -330,6 +330,36 @@ def batch_network(spec: BatchSpec, sigma: float = 1.0) -> Network:
 
 
 @dataclass
+class AnisoSpec:
+    H: float
+    ratio: float          # beta_x / beta_y of Eq. 2 (> 1: strata parallel to x)
+    index: int
+
+
+def aniso_specs(H_values: Sequence[float] = (0.75, 0.35), ratios: Sequence[float] = (1, 2, 4, 8, 16),
+                seeds: int = 16, seed_offset: int = 0) -> List[AnisoSpec]:
+    """The K_x / K_y study of Sec. VI.B (Fig. 10): for every Hurst exponent and
+    anisotropy ratio, `seeds` independent networks (seed streams 30,000,000 +)."""
+    out = []
+    k = 0
+    for H in H_values:
+        for ratio in ratios:
+            for _ in range(seeds):
+                out.append(AnisoSpec(float(H), float(ratio), 30_000_000 + seed_offset + k))
+                k += 1
+    return out
+
+
+def aniso_network(spec: AnisoSpec, n: int = 512, sigma: float = 1.5, rank_q: Optional[float] = None) -> Network:
+    """2D n x n network with the anisotropic spectrum of Eq. 2: beta_y = 1 and
+    beta_x = ratio (numpy axes are (y, x)), optionally rank-diluted (Sec. VI.B)."""
+    net = fbm_network(2, n, n, 1, H=spec.H, sigma=sigma, index=spec.index, axis=0,
+                      beta=[1.0, spec.ratio], rank_q=rank_q)
+    net.meta["ratio"] = spec.ratio
+    return net
+
+
+@dataclass
 class StreamRequest:
     t_arrival: float
     dim: int

@@ -101,3 +101,24 @@ def test_batch_and_stream_specs():
     assert 0.35 < np.mean([r.dim == 2 for r in reqs]) < 0.65
     t = np.array([r.t_arrival for r in reqs])
     assert np.all(np.diff(t) > 0)
+
+
+def test_aniso_spectrum_layers_along_x(oracle_mod):
+    """Eq. 2 with beta_x / beta_y > 1 stretches the correlations along x:
+    the field varies less from column to column than from row to row, and
+    flow along the strata (K_x) is easier than across them (K_y)."""
+    import numpy as np
+    specs = [s for s in I.aniso_specs(H_values=(0.75,), ratios=(1, 16), seeds=4)]
+    ratios = {1.0: [], 16.0: []}
+    for sp in specs:
+        net = I.aniso_network(sp, n=64)
+        lg = np.log(net.g[1][:-1, :])                     # y-bonds: ln g = sigma * mean of two node values
+        vx = np.var(np.diff(lg, axis=1))
+        vy = np.var(np.diff(lg, axis=0))
+        if sp.ratio == 16.0:
+            assert vx < 0.5 * vy
+        kx = oracle_mod.solve(net, tol=1e-12).K
+        ky = oracle_mod.solve(net.with_axis(1), tol=1e-12).K
+        ratios[sp.ratio].append(kx / ky)
+    assert np.mean(ratios[16.0]) > 1.0
+    assert np.mean(ratios[16.0]) > np.mean(ratios[1.0])
