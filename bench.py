@@ -321,6 +321,9 @@ def batch_bench(args, B, I, np):
                        "unit": "GB/s", "frac": round(bytes_m / min(walls_m) / 1e9 / HBM_PEAK_GBS, 4),
                        "traffic": None, "kernel": "pass2d/pass3d_kernel<float> (all networks per launch)",
                        "note": "algorithmic bytes of every member's passes / batch wall time"}
+    if args.no_fp64:
+        ctx.close()
+        return out
     walls_d, res_d = run(B.RN_FP64, 1)
     out["fp64_batched_solves_per_s"] = round(len(probs) / min(walls_d), 4)
     # plain FP64 CG, one network at a time

@@ -42,7 +42,7 @@ def gpu_solve(ctx, net, precision, tol=None, max_iter=500_000):
     return res, P, M
 
 
-def check_against_oracle(oracle_mod, net, res, P, M, precision, ref=None):
+def check_against_oracle(oracle_mod, net, res, P, M, precision, ref=None, pointwise=True):
     if ref is None:
         ref = oracle_mod.solve(net, tol=1e-13, want_mask=True)
     np.testing.assert_array_equal(M, ref.mask)
@@ -62,9 +62,13 @@ def check_against_oracle(oracle_mod, net, res, P, M, precision, ref=None):
     # pressures: faces and dead nodes exact, live nodes close to the oracle's
     live = ref.mask == 3
     np.testing.assert_array_equal(P[~live], ref.pressure[~live])
-    if ref.n_live:
+    if ref.n_live and pointwise:
         err = np.max(np.abs(P[live] - ref.pressure[live]))
         assert err <= 1e-4 if precision == B.RN_MIXED else err <= 1e-6
+    elif ref.n_live:
+        # the pointwise error bound depends on the conditioning; the maximum
+        # principle (pressures between the face values) holds for any network
+        assert c.p_min >= -1e-6 and c.p_max <= 1 + 1e-6
     return ref
 
 
