@@ -117,7 +117,8 @@ hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dl
 hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
 // One pass of every network in the block table blk[0..nblocks): entry
 // (network, local block); tab[2 * network + parity] are that network's
-// arguments and scal[network] its control block.
+// arguments and scal[network] its control block. dim: 2 (2D, full tiles),
+// -2 (2D, small tiles) or 3.
 template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
                        hipStream_t st);
@@ -146,6 +147,7 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
 #endif
 constexpr int kTX = 64, kTY = RN_TY3, kTZ = RN_TZ3;
 constexpr int kTY2f = RN_TY2F, kTY2d = RN_TY2D, kSEG2f = RN_SEG2F, kSEG2d = RN_SEG2D;
+constexpr int kTY2fS = 2, kTY2dS = 1;   // rows per wave of the small 2D tile (one 64-column segment)
 
 
 __host__ __device__ inline int div_up(int a, int b) { return (a + b - 1) / b; }

@@ -2,7 +2,7 @@
 // multi-network iteration engine.
 //
 // Every network in the engine owns a control-block slot. Each pass round
-// launches one pass kernel per kind (2D/3D x FP32/FP64) over a block table
+// launches one pass kernel per kind (2D full or small tiles / 3D x FP32/FP64) over a block table
 // listing (slot, local block) for every active network, so networks of any
 // size and dimension advance together while each keeps its own reduction,
 // scalars and convergence. A network's arithmetic depends only on its own
@@ -120,11 +120,8 @@ double cross_section(const rn_problem *p)
 // round): the per-workgroup tail (partials, ticket) is then paid once per two
 // tiles. Measured on the 2048^2 FP64 pass, three or four tiles per workgroup
 // were 2% slower than two.
-constexpr int kWGTarget2D = 1024, kTpwMax2D = 2;
-#ifndef RN_MIN_TZ3
-#define RN_MIN_TZ3 8
-#endif
-constexpr int kWGTarget3D = 1024, kMinTZ3D = RN_MIN_TZ3;
+constexpr int kWGTarget2D = 1024, kTpwMax2D = 2, kSmall2D = 128;
+
 
 Layout make_layout(const rn_problem *p, const rn_opts *o)
 {
@@ -134,23 +131,33 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.s = (o && o->precision == RN_MIXED) ? 4 : 8;
     L.copy_g = p->mem == RN_MEM_HOST;
     if (p->dim == 2) {
+        // full tiles unless the network has fewer than kSmall2D of them: its
+        // pass is then bound by the latency of one tile, which the
+        // quarter-size tile (64 columns, half the rows) shortens. Measured
+        // per pass: 128^2 10.2 -> 8.5 us, 256^2 9.3 -> 8.4 us; at 512^2 and
+        // 1024^2 the small tile was no faster alone and slower in batches.
         L.ntx = div_up((int)p->nx, kWave * (L.s == 4 ? kSEG2f : kSEG2d));
         L.nty = div_up((int)p->ny, (L.s == 4 ? kTY2f : kTY2d) * (kBlock / kWave));
+        L.shape = L.ntx * L.nty < kSmall2D ? 1 : 0;
+        if (L.shape) {
+            L.ntx = div_up((int)p->nx, kWave);
+            L.nty = div_up((int)p->ny, (L.s == 4 ? kTY2fS : kTY2dS) * (kBlock / kWave));
+        }
         L.ntz = 1;
         L.ntiles = L.ntx * L.nty;
         L.tpw = std::max(1, std::min(kTpwMax2D, L.ntiles / kWGTarget2D));
         L.grid = div_up(L.ntiles, L.tpw);
     } else {
-        // planes per tile: kTZ, halved (down to kMinTZ3D) while the network
-        // would have fewer than kWGTarget3D workgroups, so that a small
-        // network alone in a pass still spreads over the chip (each halving
-        // adds two halo planes per tile to the reads). On the 512-network
-        // batch a floor of 8 planes measured 3% faster than 16, and 4 no
-        // better than 8.
+        // planes per tile, by size: a tile streams its planes one after
+        // another, so a small network's pass takes as long as one tile's
+        // stream, while a large one is bound by bytes, and every tile reads
+        // two halo planes. Measured per pass (mixed): 32^3 24.1 / 16.4 /
+        // 12.8 us at 8 / 4 / 2 planes, 128^3 29.8 / 28.2 / 32.8 us, 192^3
+        // 92.7 / 96.9 us at 8 / 4; the 512-network batch was 5% slower with
+        // 2-plane tiles than with 4.
         L.ntx = div_up((int)p->nx, kTX);
         L.nty = div_up((int)p->ny, kTY);
-        L.tile_z = kTZ;
-        while (L.tile_z > kMinTZ3D && L.ntx * L.nty * div_up((int)p->nz, L.tile_z) < kWGTarget3D) L.tile_z /= 2;
+        L.tile_z = L.n >= (int64_t)12 << 20 ? kTZ : (L.n >= (int64_t)3 << 20 ? kTZ / 2 : kTZ / 4);
         L.ntz = div_up((int)p->nz, L.tile_z);
         L.ntiles = L.ntx * L.nty * L.ntz;
         L.grid = L.ntiles;
@@ -478,7 +485,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
 
 int Engine::rebuild(hipStream_t st, std::string *err)
 {
-    int count[kKinds] = {0, 0, 0, 0};
+    int count[kKinds] = {};
     for (Net *n : active_) count[n->kind] += n->L.grid;
     for (int k = 0; k < kKinds; ++k) {
         if (count[k] > blk_cap_[k]) {
@@ -517,8 +524,8 @@ int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
         const int par = (int)((rounds_ + i) & 1);
         for (int k = 0; k < kKinds; ++k) {
             if (!nblk_[k]) continue;
-            const int dim = (k & 1) ? 3 : 2;
-            if (k < 2) ENG_TRY(launch_pass<float>(dim, d_tabf_, d_blk_[k], d_scal_, nblk_[k], par, st));
+            const int dim = kind_dim(k);
+            if (!kind_fp64(k)) ENG_TRY(launch_pass<float>(dim, d_tabf_, d_blk_[k], d_scal_, nblk_[k], par, st));
             else ENG_TRY(launch_pass<double>(dim, d_tabd_, d_blk_[k], d_scal_, nblk_[k], par, st));
         }
     }

@@ -293,20 +293,24 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 // of one segment and lane 0 of the next); lanes 0..TY-1 and 64-TY..63 load the
 // halo columns x0-1 and x0+64 SEG (one row each), which shuffles hand to lane
 // 0 of the first segment and lane 63 of the last.
-template <typename T>
+// SHAPE 0: the tile for networks with enough tiles to fill the chip; SHAPE 1:
+// a quarter-size tile (one segment, half the rows) for smaller networks,
+// which would otherwise leave most CUs with one or two workgroups.
+template <typename T, int SHAPE>
 struct Tile2D {
-    static constexpr int TY = sizeof(T) == 4 ? kTY2f : kTY2d;     // rows per wave
-    static constexpr int SEG = sizeof(T) == 4 ? kSEG2f : kSEG2d;  // 64-column segments per row
-    static constexpr int ROWS = TY * (kBlock / kWave);           // rows per workgroup
-    static constexpr int COLS = kWave * SEG;                     // columns per workgroup
+    static constexpr int TY = SHAPE == 0 ? (sizeof(T) == 4 ? kTY2f : kTY2d)           // rows per wave
+                                         : (sizeof(T) == 4 ? kTY2fS : kTY2dS);
+    static constexpr int SEG = SHAPE == 0 ? (sizeof(T) == 4 ? kSEG2f : kSEG2d) : 1;   // 64-column segments per row
+    static constexpr int ROWS = TY * (kBlock / kWave);                                // rows per workgroup
+    static constexpr int COLS = kWave * SEG;                                          // columns per workgroup
 };
 
-template <typename T>
+template <typename T, int SHAPE>
 __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int yb, int lane,
                                           int w, T alpha, T beta, double sa, double (&acc)[kRed])
 {
-    constexpr int TY = Tile2D<T>::TY;
-    constexpr int SEG = Tile2D<T>::SEG;
+    constexpr int TY = Tile2D<T, SHAPE>::TY;
+    constexpr int SEG = Tile2D<T, SHAPE>::SEG;
     constexpr int NW = kBlock / kWave;
     __shared__ T edge[2][NW][SEG][kWave];   // [0]: first row of each wave, [1]: last row
     const int nx = a.nx, ny = a.ny;
@@ -393,7 +397,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     // halo columns: lane l < TY holds (x0-1, y0+l), lane 64-TY+l holds (x0+64 SEG, y0+l)
     const bool hleft = lane < TY, hright = lane >= kWave - TY;
     const int hr_ = hleft ? lane : lane - (kWave - TY);
-    const int hx = colm(hleft ? x0 - 1 : x0 + Tile2D<T>::COLS);
+    const int hx = colm(hleft ? x0 - 1 : x0 + Tile2D<T, SHAPE>::COLS);
     const bool hok = (hleft || hright) && hx >= 0 && y0 + hr_ < ny;
     T hd = T(0), hr = T(0), hq = T(0), hp = T(0), hg = T(0);
     {
@@ -489,7 +493,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 // has its own arguments (two parities of the double-buffered state), partial
 // sums, ticket and control block, so networks advance independently and a
 // network's arithmetic does not depend on what else is in the launch.
-template <typename T>
+template <typename T, int SHAPE>
 __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__restrict__ tab,
                                                         const uint2 *__restrict__ blk, Scalars *scal, int parity)
 {
@@ -510,15 +514,15 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
         if (tile >= a.ntiles) break;
         if (k > 0) __syncthreads();              // the previous tile's LDS rows are reused
         const int tx = tile % a.ntx, ty = tile / a.ntx;
-        const int x0 = tx * Tile2D<T>::COLS;
-        const int yb = ty * Tile2D<T>::ROWS;
+        const int x0 = tx * Tile2D<T, SHAPE>::COLS;
+        const int yb = ty * Tile2D<T, SHAPE>::ROWS;
         if (mode == MODE_CG) {
-            cg2d_tile<T>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
+            cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
         } else {
             const double sigma_next = s->sigma_next;
-            const int y0 = yb + w * Tile2D<T>::TY;
-            const int y1 = min(y0 + Tile2D<T>::TY, a.ny);
-            for (int sg = 0; sg < Tile2D<T>::SEG; ++sg) {
+            const int y0 = yb + w * Tile2D<T, SHAPE>::TY;
+            const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
+            for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
                 const int x = x0 + kWave * sg + lane;
                 if (x < a.nx)
                     for (int yy = y0; yy < y1; ++yy)
@@ -1064,7 +1068,8 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
                        hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (dim == 2) pass2d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
+    if (dim == 2) pass2d_kernel<T, 0><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
+    else if (dim == -2) pass2d_kernel<T, 1><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
     else pass3d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
     return hipGetLastError();
 }

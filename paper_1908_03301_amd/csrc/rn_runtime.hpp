@@ -52,6 +52,7 @@ struct Layout {
     int dim = 2, s = 8;
     bool copy_g = false;
     int grid = 8, groups = 1, tpw = 1, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_z = 16;
+    int shape = 0;   // 2D tile: 0 full, 1 small
     size_t off_g64 = 0, off_P = 0, off_dl = 0, off_mask = 0, off_gT = 0, off_invd = 0, off_vec = 0,
            off_part = 0, off_tk = 0, off_cnt = 0, total = 0;
 };
@@ -67,7 +68,7 @@ struct Net {
     char *base = nullptr;           // device arena (pool)
     const double *gd[3] = {nullptr, nullptr, nullptr};
     int slot = -1;                  // control block / descriptor slot in the engine
-    int kind = 0;                   // 2D/3D x FP32/FP64, see Engine::kind_of
+    int kind = 0;                   // tile family x FP32/FP64, see Engine::kind_of
     NetPhase phase = NET_NEW;
     int64_t n_live = 0;
     int64_t na = 0;                 // extent along the flow axis
@@ -89,7 +90,8 @@ struct Net {
 class Engine {
 public:
     static constexpr int kSlots = 4096;
-    static constexpr int kKinds = 4;   // (dim 2 | 3) x (fp32 | fp64)
+    // kinds: 0 2D full tiles, 1 3D, 2 and 3 the same in FP64, 4 2D small tiles, 5 the same in FP64
+    static constexpr int kKinds = 6;
 
     int init(hipStream_t st, std::string *err);
     void destroy();
@@ -116,7 +118,14 @@ public:
     void abort_all();
 
 private:
-    int kind_of(const Net *n) const { return (n->prob.dim == 3 ? 1 : 0) + (n->L.s == 8 ? 2 : 0); }
+    int kind_of(const Net *n) const
+    {
+        const int fp64 = n->L.s == 8 ? 1 : 0;
+        if (n->prob.dim == 3) return 1 + 2 * fp64;
+        return n->L.shape ? 4 + fp64 : 2 * fp64;
+    }
+    static bool kind_fp64(int k) { return k == 2 || k == 3 || k == 5; }
+    static int kind_dim(int k) { return (k == 1 || k == 3) ? 3 : (k >= 4 ? -2 : 2); }   // launch_pass's dim
     int rebuild(hipStream_t st, std::string *err);
     int finalize(Net *net, const Scalars &h, hipStream_t st, std::string *err);
 
@@ -124,10 +133,10 @@ private:
     PassArgs<float> *d_tabf_ = nullptr, *h_tabf_ = nullptr;
     PassArgs<double> *d_tabd_ = nullptr, *h_tabd_ = nullptr;
     unsigned long long *h_cnt_ = nullptr;   // [kSlots][4] pinned
-    uint2 *d_blk_[kKinds] = {nullptr, nullptr, nullptr, nullptr};
-    uint2 *h_blk_[kKinds] = {nullptr, nullptr, nullptr, nullptr};
-    int blk_cap_[kKinds] = {0, 0, 0, 0};
-    int nblk_[kKinds] = {0, 0, 0, 0};
+    uint2 *d_blk_[kKinds] = {};
+    uint2 *h_blk_[kKinds] = {};
+    int blk_cap_[kKinds] = {};
+    int nblk_[kKinds] = {};
     hipEvent_t ev_chunk_[2] = {nullptr, nullptr};
     std::deque<int> outstanding_;           // mirrors with a queued status read, oldest first
     int next_mirror_ = 0, half_ = 0;
