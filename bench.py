@@ -215,6 +215,23 @@ def main():
     out["results"] = {f"K_axis{ax}": r["K"] for ax, r in res_m[: len(wl["axes"])]}
     out["iters_mixed"] = {f"axis{ax}": r["iters"] for ax, r in res_m[: len(wl["axes"])]}
 
+    if len(probs) > 1:
+        # context: every axis of the network in one rn_solve_batch, so that
+        # the passes of the solves share launches (not the headline value)
+        walls = []
+        for it in range(args.warmup + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rb = ctx.solve_batch([pr for _, pr in probs], B.opts(B.RN_MIXED, args.tol))
+            w = time.perf_counter() - t
+            if any(r.status != 0 or not r.converged for r in rb):
+                raise SystemExit("batched axes failed")
+            if it >= args.warmup:
+                walls.append(w)
+        out["axes_batched"] = {"solves_per_s": round(len(probs) / min(walls), 4),
+                               "wall_ms": round(1e3 * min(walls), 3),
+                               "K": {f"axis{ax}": r.K for (ax, _), r in zip(probs, rb)}}
+
     if not args.no_fp64:
         lat_d, res_d = leg(B.RN_FP64)
         pbd = pass_bytes(net.dim, n, 8, res_d[0][1]["n_live"])

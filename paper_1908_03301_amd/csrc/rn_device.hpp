@@ -118,10 +118,11 @@ hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipSt
 // One pass of every network in the block table blk[0..nblocks): entry
 // (network, local block); tab[2 * network + parity] are that network's
 // arguments and scal[network] its control block. dim: 2 (2D, full tiles),
-// -2 (2D, small tiles) or 3.
+// -2 (2D, small tiles) or 3. With blk == nullptr the launch covers the one
+// network in `slot`, local block = blockIdx.x.
 template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
-                       hipStream_t st);
+                       int slot, hipStream_t st);
 
 // tile geometry of the pass kernels: a 2D workgroup tile is 64 kSEG2f x
 // 4 kTY2f (FP32) or 64 kSEG2d x 4 kTY2d (FP64): each wave holds kTY2f / kTY2d

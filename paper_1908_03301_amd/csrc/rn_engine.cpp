@@ -505,7 +505,15 @@ int Engine::rebuild(hipStream_t st, std::string *err)
     half_ ^= 1;
     for (int k = 0; k < kKinds; ++k) {
         nblk_[k] = count[k];
+        single_[k] = -1;
         if (!count[k]) continue;
+        int nets = 0;
+        for (Net *n : active_)
+            if (n->kind == k) {
+                ++nets;
+                single_[k] = n->slot;
+            }
+        if (nets != 1) single_[k] = -1;
         uint2 *h = h_blk_[k] + (size_t)half_ * blk_cap_[k];
         int m = 0;
         for (Net *n : active_)
@@ -525,8 +533,11 @@ int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
         for (int k = 0; k < kKinds; ++k) {
             if (!nblk_[k]) continue;
             const int dim = kind_dim(k);
-            if (!kind_fp64(k)) ENG_TRY(launch_pass<float>(dim, d_tabf_, d_blk_[k], d_scal_, nblk_[k], par, st));
-            else ENG_TRY(launch_pass<double>(dim, d_tabd_, d_blk_[k], d_scal_, nblk_[k], par, st));
+            const uint2 *blk = single_[k] >= 0 ? nullptr : d_blk_[k];
+            if (!kind_fp64(k))
+                ENG_TRY(launch_pass<float>(dim, d_tabf_, blk, d_scal_, nblk_[k], par, single_[k], st));
+            else
+                ENG_TRY(launch_pass<double>(dim, d_tabd_, blk, d_scal_, nblk_[k], par, single_[k], st));
         }
     }
     return RN_OK;

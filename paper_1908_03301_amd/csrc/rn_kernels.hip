@@ -16,9 +16,10 @@
 // next step without a second reduction. The solution is accumulated straight
 // into the FP64 pressure field every pass: an FP32 accumulator would round the
 // correction by 2^-24 of its size, i.e. a residual error of order 2^-24 times
-// the condition number at every refresh. Nodes outside the live set read only
-// 1/d (0 there) and write nothing. r, p, q are double-buffered because
-// neighbours read them from the previous pass.
+// the condition number at every refresh. Nodes outside the live set hold
+// r = p = q = 0 and 1/d = 0, so the same arithmetic keeps them at zero; they
+// are read and stored like the others so that cache lines move whole. r, p, q
+// are double-buffered because neighbours read them from the previous pass.
 //
 // The same kernel, in refresh mode, evaluates the FP64 true residual b - A x
 // of the pressure field with the original conductances, the face fluxes and
@@ -495,9 +496,12 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 // network's arithmetic does not depend on what else is in the launch.
 template <typename T, int SHAPE>
 __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__restrict__ tab,
-                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity)
+                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity,
+                                                        int slot)
 {
-    const uint2 e = blk[blockIdx.x];
+    // a launch of one network passes its slot instead of a block table, which
+    // saves a dependent load at the start of every workgroup
+    const uint2 e = blk ? blk[blockIdx.x] : make_uint2((unsigned)slot, blockIdx.x);
     const PassArgs<T> &a = tab[2 * e.x + parity];
     const int lb = (int)e.y;
     Scalars *s = scal + e.x;          // == a.s; indexed directly to shorten the load chain
@@ -762,9 +766,12 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__restrict__ tab,
-                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity)
+                                                        const uint2 *__restrict__ blk, Scalars *scal, int parity,
+                                                        int slot)
 {
-    const uint2 e = blk[blockIdx.x];
+    // a launch of one network passes its slot instead of a block table, which
+    // saves a dependent load at the start of every workgroup
+    const uint2 e = blk ? blk[blockIdx.x] : make_uint2((unsigned)slot, blockIdx.x);
     const PassArgs<T> &a = tab[2 * e.x + parity];
     const int lb = (int)e.y;
     Scalars *s = scal + e.x;          // == a.s; indexed directly to shorten the load chain
@@ -1065,12 +1072,12 @@ hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipSt
 
 template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
-                       hipStream_t st)
+                       int slot, hipStream_t st)
 {
     if (nblocks <= 0) return hipSuccess;
-    if (dim == 2) pass2d_kernel<T, 0><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
-    else if (dim == -2) pass2d_kernel<T, 1><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
-    else pass3d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity);
+    if (dim == 2) pass2d_kernel<T, 0><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity, slot);
+    else if (dim == -2) pass2d_kernel<T, 1><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity, slot);
+    else pass3d_kernel<T><<<nblocks, kBlock, 0, st>>>(tab, blk, scal, parity, slot);
     return hipGetLastError();
 }
 
@@ -1078,9 +1085,9 @@ template hipError_t launch_scale<float>(const Lat &, const double *const[3], con
                                         float *, float *, int64_t, hipStream_t);
 template hipError_t launch_scale<double>(const Lat &, const double *const[3], const double *, double *const[3],
                                          double *, double *, int64_t, hipStream_t);
-template hipError_t launch_pass<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int,
+template hipError_t launch_pass<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int, int,
                                        hipStream_t);
-template hipError_t launch_pass<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int,
+template hipError_t launch_pass<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int, int,
                                         hipStream_t);
 
 }  // namespace rn

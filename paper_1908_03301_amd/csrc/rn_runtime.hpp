@@ -137,6 +137,7 @@ private:
     uint2 *h_blk_[kKinds] = {};
     int blk_cap_[kKinds] = {};
     int nblk_[kKinds] = {};
+    int single_[kKinds] = {};              // slot of the only network of a kind, or -1
     hipEvent_t ev_chunk_[2] = {nullptr, nullptr};
     std::deque<int> outstanding_;           // mirrors with a queued status read, oldest first
     int next_mirror_ = 0, half_ = 0;
