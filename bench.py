@@ -47,6 +47,9 @@ MULTI = {
     "aniso": "permeability anisotropy study (Eq. 2, Fig. 10): 2D 512x512 FBM ln g (sigma=1.5) with "
              "beta_x/beta_y in {1,2,4,8,16} and H in {0.75,0.35}, 16 networks each, K_x and K_y of every "
              "network in one batch",
+    "fbmgen": "network generation (Eqs. 1-2, Table I's task): FBM node field by Fourier filtering, bonds and "
+              "i.i.d. dilution for 2D 2048x2048 and 3D 256^3, on the GPU (random numbers resident in HBM) "
+              "and with numpy on one core",
 }
 
 
@@ -157,7 +160,8 @@ def main():
         return
 
     if args.workload in MULTI:
-        run = {"batch512": batch_bench, "serve": serve_bench, "aniso": aniso_bench}[args.workload]
+        run = {"batch512": batch_bench, "serve": serve_bench, "aniso": aniso_bench,
+               "fbmgen": fbmgen_bench}[args.workload]
         out = run(args, B, I, np)
         print(json.dumps(out), flush=True)
         return
@@ -392,6 +396,52 @@ def aniso_bench(args, B, I, np):
                      "nodes": sum(n.n for n in nets), "tol": args.tol,
                      "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"})
     out["Kx_over_Ky"] = summary
+    return out
+
+
+def fbmgen_bench(args, B, I, np):
+    """Nodes generated per second: field + bonds + dilution, GPU (rn_fbm_field,
+    rn_fbm_bonds) against the numpy generator, on the same random numbers."""
+    import torch
+    ctx = B.Context(0)
+    rows = {}
+    for dim, shape, H in ((2, (2048, 2048), 0.7), (3, (256, 256, 256), 0.8)):
+        rng = I.rng_for(123)
+        noise = rng.standard_normal(shape)
+        u = [rng.random(shape) for _ in range(dim)]
+        n = int(np.prod(shape))
+        nx, ny, nz = shape[-1], shape[-2], (shape[0] if dim == 3 else 1)
+        nd = torch.from_numpy(noise).cuda()
+        ud = [torch.from_numpy(a).cuda() for a in u]
+        phi = torch.empty_like(nd)
+        g = [torch.empty_like(nd) for _ in range(dim)]
+        walls = []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.fbm_field(dim, nx, ny, nz, H, nd, phi)
+            ctx.fbm_bonds(dim, nx, ny, nz, phi, 1.5, False, g, u=ud, occupancy=0.6)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                walls.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        ref = I.bonds_from_node_field(I.fbm_filter(noise, H), 1.5)
+        ref = [np.where(uk < 0.6, a, 0.0) for uk, a in zip(u, ref)]
+        t_np = time.perf_counter() - t
+        err = max(float(np.max(np.abs(a.cpu().numpy() - r) / np.maximum(r, 1e-300))) for a, r in zip(g, ref))
+        rows[f"{dim}D {'x'.join(map(str, shape[::-1]))}"] = {
+            "gpu_ms": round(1e3 * min(walls), 3), "numpy_s": round(t_np, 3),
+            "gpu_nodes_per_s": round(n / min(walls)), "numpy_nodes_per_s": round(n / t_np),
+            "speedup": round(t_np / min(walls), 1), "max_rel_diff_bonds": err}
+        print(f"[bench] fbmgen {dim}D: gpu {1e3 * min(walls):.2f} ms, numpy {t_np:.2f} s", file=sys.stderr,
+              flush=True)
+    ctx.close()
+    total_n = sum(v["gpu_nodes_per_s"] * v["gpu_ms"] / 1e3 for v in rows.values())
+    total_t = sum(v["gpu_ms"] / 1e3 for v in rows.values())
+    out = _contract(args, total_n / total_t, "nodes/s", total_t, args.steps,
+                    {"workload": MULTI["fbmgen"], "inputs": "random numbers resident in HBM"}, dtype="f64")
+    out["metric"] = "network generation nodes/s (FBM field + bonds + dilution)"
+    out["cases"] = rows
     return out
 
 

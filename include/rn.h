@@ -243,6 +243,44 @@ typedef struct {
 
 int rn_stats(rn_ctx *ctx, rn_stats_t *out);
 
+/* ------------------------------------------------------------------ inputs on the GPU
+ * Correlated conductance fields (Sec. II, Eqs. 1-2), the input generation the
+ * paper distributes over MPI processes (Sec. II, Table I), on one GPU. The
+ * random numbers are the caller's: white normals for the field, uniforms for
+ * the dilution. These calls are independent of the solve. Arrays use the
+ * lattice layout above and live in the memory space named by `mem`
+ * (RN_MEM_HOST or RN_MEM_DEVICE). Both calls return RN_EINVAL while the
+ * request server runs. The FFT plans are hipFFT's; their work areas are
+ * outside the context's budget.
+ */
+
+/*
+ * Node field by Fourier filtering on the periodic node grid (dim 2: nz = 1):
+ * the white normals `noise` (one per node) are transformed, each mode is
+ * multiplied by (sum_k beta[k] f_k^2)^(-(H + dim/2) / 2), with f_k the mode's
+ * frequency along direction k in cycles per node (f = j/n for j <= (n-1)/2,
+ * else (j - n)/n), the k = 0 mode is removed, and the inverse transform is
+ * standardised to mean 0 and population standard deviation 1 (all zeros if it
+ * is constant). For dim = 2 the exponent is Eq. 1's H + 1; beta (NULL: all 1,
+ * else beta[k] > 0 for k < dim) gives Eq. 2's anisotropic spectrum.
+ * field_out may equal noise. RN_EINVAL on a bad shape (as rn_problem), a
+ * non-finite H or a bad beta; RN_ENOMEM / RN_EDEVICE otherwise.
+ */
+int rn_fbm_field(rn_ctx *ctx, int32_t dim, int64_t nx, int64_t ny, int64_t nz, double H, const double *beta,
+                 const double *noise, double *field_out, int32_t mem);
+
+/*
+ * Bond conductances from a node field: g_out[k][i] = exp(sigma (phi_i +
+ * phi_j) / 2) for the bond from node i to j = i + e_k, j taken on the
+ * periodic grid. The last-plane entries along k are kept when `periodic` is 1
+ * (the wrap bonds of RN_PERIODIC) and set to 0 when it is 0. With u non-NULL,
+ * u[k] (k < dim, one uniform per entry) dilutes the bonds: an entry is kept
+ * where u[k][i] < occupancy and set to 0 elsewhere. RN_EINVAL on a bad shape,
+ * a non-finite sigma or occupancy, periodic not 0/1, or a NULL array.
+ */
+int rn_fbm_bonds(rn_ctx *ctx, int32_t dim, int64_t nx, int64_t ny, int64_t nz, const double *field, double sigma,
+                 int32_t periodic, const double *const u[3], double occupancy, double *const g_out[3], int32_t mem);
+
 #ifdef __cplusplus
 }
 #endif

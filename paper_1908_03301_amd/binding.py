@@ -24,7 +24,7 @@ RN_PERIODIC = 1
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
-            "rn_submit", "rn_poll", "rn_stats"]
+            "rn_submit", "rn_poll", "rn_stats", "rn_fbm_field", "rn_fbm_bonds"]
 
 
 class rn_problem(C.Structure):
@@ -94,8 +94,13 @@ def lib():
         L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
         L.rn_poll.argtypes = [C.c_void_p, C.c_uint64, P(rn_result)]
         L.rn_stats.argtypes = [C.c_void_p, P(rn_stats_t)]
+        D, DA3 = P(C.c_double), C.c_void_p * 3
+        L.rn_fbm_field.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_double, D, C.c_void_p, C.c_void_p,
+                                   C.c_int32]
+        L.rn_fbm_bonds.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_void_p, C.c_double, C.c_int32,
+                                   P(DA3), C.c_double, P(DA3), C.c_int32]
         for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve",
-                  "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats"):
+                  "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_fbm_field", "rn_fbm_bonds"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -209,6 +214,41 @@ class Context:
 
     def footprint(self, prob: Problem, o: Optional[rn_opts] = None) -> int:
         return int(lib().rn_footprint(C.byref(prob.c), C.byref(o) if o is not None else None))
+
+    def fbm_field(self, dim: int, nx: int, ny: int, nz: int, H: float, noise, out, beta=None):
+        """rn_fbm_field: `noise` and `out` are float64 numpy arrays (host) or
+        contiguous float64 CUDA tensors (device) of nx*ny*nz nodes; `beta` per
+        lattice direction (x, y, z) or None."""
+        dev = _is_torch(noise)
+        ptr = (lambda a: a.data_ptr()) if dev else (lambda a: a.ctypes.data)
+        if not dev:
+            for a in (noise, out):
+                if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
+                    raise ValueError("host arrays must be C-contiguous float64")
+        b = (C.c_double * 3)(*([float(v) for v in beta] + [1.0] * (3 - len(beta)))) if beta is not None else None
+        st = lib().rn_fbm_field(self.h, int(dim), int(nx), int(ny), int(nz), float(H), b, C.c_void_p(ptr(noise)),
+                                C.c_void_p(ptr(out)), RN_MEM_DEVICE if dev else RN_MEM_HOST)
+        if st:
+            raise RNError(st, self.last_error())
+
+    def fbm_bonds(self, dim: int, nx: int, ny: int, nz: int, field, sigma: float, periodic: bool, g_out,
+                  u=None, occupancy: float = 1.0):
+        """rn_fbm_bonds: `g_out` (and `u` when given) hold dim arrays like `field`."""
+        dev = _is_torch(field)
+        ptr = (lambda a: a.data_ptr()) if dev else (lambda a: a.ctypes.data)
+        arrs = [field] + list(g_out) + (list(u) if u is not None else [])
+        if not dev:
+            for a in arrs:
+                if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
+                    raise ValueError("host arrays must be C-contiguous float64")
+        DA3 = C.c_void_p * 3
+        g3 = DA3(*([ptr(a) for a in g_out] + [None] * (3 - len(g_out))))
+        u3 = DA3(*([ptr(a) for a in u] + [None] * (3 - len(u)))) if u is not None else None
+        st = lib().rn_fbm_bonds(self.h, int(dim), int(nx), int(ny), int(nz), C.c_void_p(ptr(field)), float(sigma),
+                                int(bool(periodic)), C.byref(u3) if u3 is not None else None, float(occupancy),
+                                C.byref(g3), RN_MEM_DEVICE if dev else RN_MEM_HOST)
+        if st:
+            raise RNError(st, self.last_error())
 
     def build_mask(self, prob: Problem) -> int:
         nl = C.c_int64(0)

@@ -389,6 +389,7 @@ int rn_destroy(rn_ctx *ctx)
     }
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    fbm_release(ctx);
     Sched *S = nullptr;
     {
         std::lock_guard<std::mutex> lk(g_sched_mu);

@@ -182,9 +182,11 @@ struct rn_ctx {
     std::mutex call_mu;             // serialises the synchronous entry points with the server
     std::atomic<int> callers{0};    // threads waiting for call_mu (the server steps aside for them)
     rn_server *server = nullptr;
+    void *fbm_plans = nullptr;      // FFT plans of the last generated grid (rn_fbm.hip)
 };
 
 namespace rn {
+void fbm_release(rn_ctx *ctx);   // frees ctx->fbm_plans (rn_fbm.hip)
 int check_shape(const rn_problem *p);
 int check_opts(const rn_opts *o);
 bool host_values_ok(const rn_problem *p);

@@ -119,8 +119,14 @@ def fbm_field(shape: Sequence[int], H: float, rng: np.random.Generator,
     anisotropy factor of each numpy axis (default all 1).
     """
     shape = tuple(int(s) for s in shape)
-    d = len(shape)
     noise = rng.standard_normal(shape)
+    return fbm_filter(noise, H, beta)
+
+
+def fbm_filter(noise: np.ndarray, H: float, beta: Optional[Sequence[float]] = None) -> np.ndarray:
+    """The filtering step of `fbm_field` on given white noise (see there)."""
+    shape = noise.shape
+    d = len(shape)
     spec = np.fft.fftn(noise)
     if beta is None:
         beta = [1.0] * d

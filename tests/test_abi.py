@@ -139,3 +139,14 @@ def test_batch_and_serve_argument_checks(lib):
     assert lib.rn_submit(None, C.byref(_prob().c), None, C.byref(t)) == B.RN_EINVAL
     assert lib.rn_poll(None, 1, C.byref(B.rn_result())) == B.RN_EINVAL
     assert lib.rn_stats(None, C.byref(B.rn_stats_t())) == B.RN_EINVAL
+
+
+def test_fbm_entry_points_reject_bad_arguments(lib):
+    import ctypes as C
+    L = B.lib()
+    x = np.zeros(16)
+    p = C.c_void_p(x.ctypes.data)
+    assert L.rn_fbm_field(None, 2, 4, 4, 1, 0.7, None, p, p, B.RN_MEM_HOST) == B.RN_EINVAL
+    DA3 = C.c_void_p * 3
+    g = DA3(x.ctypes.data, x.ctypes.data, None)
+    assert L.rn_fbm_bonds(None, 2, 4, 4, 1, p, 1.0, 0, None, 1.0, C.byref(g), B.RN_MEM_HOST) == B.RN_EINVAL
