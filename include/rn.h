@@ -110,7 +110,8 @@ typedef struct {
     double K;           /* Darcy K of Eq. 4: G (n_axis - 1) / S */
     double rel_resid;   /* final ||b - A x|| / ||b|| in FP64 (0 when nothing is live) */
     int64_t iters;      /* CG iterations */
-    int64_t refreshes;  /* FP64 true-residual refreshes (the first one computes b) */
+    int64_t refreshes;  /* FP64 true-residual refreshes (the first computes b, the second the
+                           residual of the initial guess, the linear profile along the axis) */
     int64_t n_live;     /* interior nodes connected to both faces */
     int64_t passes;     /* pass rounds launched while this network iterated (a round launches
                            one pass kernel per kind of network present; idle rounds after

@@ -106,6 +106,8 @@ __device__ void step_after_cg(Scalars *s, const double *t)
 }
 
 // Scalar update after a refresh pass. t = (||r64||^2, r.D^-1 r of the stored residual, x.r64, Q_in, Q_out).
+// s->first: 1 before the refresh that evaluates b, 2 before the one that
+// evaluates the residual of the initial guess, 0 afterwards.
 __device__ void step_after_refresh(Scalars *s, const double *t)
 {
     const double rr64 = t[0], rrs = t[1];
@@ -114,13 +116,34 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
     const double sigma_old = s->sigma;
     const double sigma = s->sigma_next;
     s->sigma = sigma;
-    const bool first = s->first != 0;
-    if (first) {
+    const int first = s->first;
+    if (first == 1) {
+        // this refresh evaluated b alone (the inflow at x = 0): fix the norms the
+        // stopping rule and the estimates refer to, then evaluate the residual
+        // of the initial guess (the linear profile along the flow axis)
         s->bnorm = sqrt(rr64);
         s->bhat = sigma * sqrt(rrs);
         s->kappa = 1.0;
-        s->first = 0;
+        s->xr = t[2];
+        s->Q_in = t[3];
+        s->Q_out = t[4];
+        if (!(s->bnorm > 0.0) || !isfinite(rr64) || !isfinite(rrs)) {
+            if (s->bnorm == 0.0) s->converged = 1;      // nothing flows in
+            else s->status = -4;
+            s->rel_resid = s->est_rel = 0.0;
+            s->mode = MODE_DONE;
+        } else {
+            s->first = 2;
+            s->rel_resid = s->est_rel = 1.0;
+            s->alpha = 0.0;
+            s->sigma_next = sigma;
+            s->mode = MODE_REFRESH;
+        }
+        s->check = 0;
+        return;
     }
+    const bool restart = first == 2;             // the first residual: start the recurrence
+    s->first = 0;
     const double rel = s->bnorm > 0.0 ? sqrt(rr64) / s->bnorm : 0.0;
     const double srel = s->bhat > 0.0 ? sigma * sqrt(rrs) / s->bhat : 0.0;
     if (srel > 0.0 && rel > 0.0) s->kappa = rel / srel;
@@ -149,7 +172,7 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
         if (s->check) s->last_check = rel;
         s->mode = MODE_CG;
         s->alpha = 0.0;
-        s->beta = first ? 0.0 : sigma * rrs / (sigma_old * s->rho);
+        s->beta = restart ? 0.0 : sigma * rrs / (sigma_old * s->rho);
         s->rmax = sqrt(rrs);
     }
     s->check = 0;
@@ -231,7 +254,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
 template <typename T, int DIM>
 __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
                                              double *__restrict__ Pd, int x, int y, int z, double sa,
-                                             double sigma_next, double (&acc)[kRed])
+                                             double sigma_next, bool bonly, double (&acc)[kRed])
 {
     const int64_t sx = 1, sy = a.nx, sz = (int64_t)a.nx * a.ny;
     const int64_t i = x + sy * y + sz * z;
@@ -240,8 +263,10 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
         Pd[i] = Ps[i];
         return;
     }
+    // bonly: evaluate b = b - A 0, the interior pressures taken as 0 and the
+    // inlet face at 1 (the first refresh of a solve)
     auto pn = [&](int64_t j) -> double { return Ps[j] + sa * (double)a.src.p[j]; };
-    const double pi = pn(i);
+    const double pi = bonly ? 0.0 : pn(i);
     double r64 = 0.0, qin = 0.0, qout = 0.0;
     const int c[3] = {x, y, z};
     const int n[3] = {a.nx, a.ny, a.nz};
@@ -254,21 +279,22 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
             const int64_t j = c[k] > 0 ? i - st[k] : i + span;
             const double g = a.g64[k][j];
             if (g != 0.0) {
-                r64 += g * (pn(j) - pi);
-                if (k == a.axis && c[k] == 1) qin += g * (1.0 - pi);
+                const bool inlet = k == a.axis && c[k] == 1;
+                r64 += g * ((bonly ? (inlet ? 1.0 : 0.0) : pn(j)) - pi);
+                if (inlet) qin += g * (1.0 - pi);
             }
         }
         if (c[k] + 1 < n[k] || wk) {
             const int64_t j = c[k] + 1 < n[k] ? i + st[k] : i - span;
             const double g = a.g64[k][i];
             if (g != 0.0) {
-                r64 += g * (pn(j) - pi);
+                r64 += g * ((bonly ? 0.0 : pn(j)) - pi);
                 if (k == a.axis && c[k] == n[k] - 2) qout += g * pi;
             }
         }
     }
     const T rs = (T)(r64 / sigma_next);
-    Pd[i] = pi;
+    Pd[i] = bonly ? Ps[i] : pi;
     a.dst.r[i] = rs;
     a.dst.p[i] = a.src.p[i];
     a.dst.q[i] = T(0);
@@ -524,13 +550,14 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
             cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
         } else {
             const double sigma_next = s->sigma_next;
+            const bool bonly = s->first == 1;
             const int y0 = yb + w * Tile2D<T, SHAPE>::TY;
             const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
             for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
                 const int x = x0 + kWave * sg + lane;
                 if (x < a.nx)
                     for (int yy = y0; yy < y1; ++yy)
-                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, acc);
+                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, bonly, acc);
             }
         }
     }
@@ -793,13 +820,14 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
         } else {
             const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
             const double sigma_next = s->sigma_next;
+            const bool bonly = s->first == 1;
             const int x = x0 + lane;
             if (x < a.nx)
                 for (int j = 0; j < kRows; ++j) {
                     const int yy = y0 + w * kRows + j;
                     if (yy >= a.ny) break;
                     for (int zz = z0; zz < z1; ++zz)
-                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, sa, sigma_next, acc);
+                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, sa, sigma_next, bonly, acc);
                 }
         }
     }
@@ -934,7 +962,8 @@ __global__ void uf_flags_kernel(Lat L, const double *ga, int *parent, unsigned *
 }
 
 // Mask byte, diagonal d_i (live nodes, 0 elsewhere), initial pressure field
-// (faces 1 / 0, dead nodes 1 when tied to the inlet only, live nodes 0) and
+// (faces 1 / 0, dead nodes 1 when tied to the inlet only, live nodes the
+// linear profile 1 - c_axis / (n_axis - 1), the CG's initial guess) and
 // the live count.
 __global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, const double *g2,
                                   int *parent, const unsigned *flags, uint8_t *mask, double *dlive,
@@ -959,6 +988,11 @@ __global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, con
         } else {
             m = (uint8_t)flags[uf_find(parent, (int)i)];
             p0 = (m == 1) ? 1.0 : 0.0;
+            if (m == 3) {   // initial guess on the live set: the linear profile along the flow axis
+                const int ca = L.axis == 0 ? x : (L.axis == 1 ? y : z);
+                const int na = L.axis == 0 ? L.nx : (L.axis == 1 ? L.ny : L.nz);
+                p0 = 1.0 - (double)ca / (double)(na - 1);
+            }
             if (m == 3) {
                 const int c[3] = {x, y, z};
                 const int n[3] = {L.nx, L.ny, L.nz};
