@@ -148,6 +148,18 @@ def test_fbm_diluted_3d(ctx, oracle_mod, case, precision):
         check_against_oracle(oracle_mod, net, res, P, M, precision)
 
 
+@pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
+def test_high_contrast(ctx, oracle_mod, precision):
+    """ln g with sigma = 3.5 (conductances over about twelve orders of
+    magnitude), 2D and 3D: the FP32 inner solve still reaches the FP64 bars."""
+    for net in (I.fbm_network(2, 150, 120, 1, H=0.5, sigma=3.5, occupancy=0.8, index=1200),
+                I.iid_network(3, 30, 26, 22, sigma=3.5, occupancy=0.75, index=1201)):
+        for axis in range(net.dim):
+            n2 = net.with_axis(axis)
+            res, P, M = gpu_solve(ctx, n2, precision)
+            check_against_oracle(oracle_mod, n2, res, P, M, precision, pointwise=False)
+
+
 def test_stratified_near_threshold_3d(ctx, oracle_mod):
     net = I.stratified_network(48, H=0.8, sigma=2.0, occupancy=0.3, index=7)
     for axis in (0, 2):
