@@ -56,15 +56,15 @@ MULTI = {
 def pass_bytes(dim: int, n: int, s: int, live: int) -> dict:
     """Algorithmic HBM bytes of one pass kernel launch.
 
-    CG pass: every node reads 1/d (s bytes); a live node also reads r, p, q
-    and dim conductance arrays (s bytes each) and its FP64 pressure, and
-    writes r, p, q and the pressure: (dim + 6) s + 16 bytes. Refresh pass:
-    every node reads 1/d and copies its FP64 pressure (16 bytes); a live node
-    also reads dim FP64 conductances and p and writes r, p, q:
-    8 dim + 4 s bytes more.
+    CG pass: a live node reads z, p, u and dim conductance arrays (s bytes
+    each) and its FP64 pressure, and writes z, p, u and the pressure:
+    (dim + 6) s + 16 bytes; its Jacobi diagonal is the sum of the bonds it
+    reads. Refresh pass: every node copies its FP64 pressure (16 bytes) and
+    reads its dim inner-precision bonds (s each); a live node also reads dim
+    FP64 conductances and p and writes z, p, u: 8 dim + 4 s bytes more.
     """
-    return {"cg": s * n + ((dim + 6) * s + 16) * live,
-            "refresh": (s + 16) * n + (8 * dim + 4 * s) * live}
+    return {"cg": ((dim + 6) * s + 16) * live,
+            "refresh": (16 + dim * s) * n + (8 * dim + 4 * s) * live}
 
 
 def cpu_info() -> str:

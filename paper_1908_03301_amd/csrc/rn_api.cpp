@@ -451,14 +451,13 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
     std::lock_guard<std::mutex> lk(ctx->call_mu);
     if (ctx->server) return RN_EINVAL;        // the server owns the stream once started
     RN_TRY(hipSetDevice(ctx->device));
-    // the mask needs the FP64 bonds (host input), the field and diagonal
-    // scratch, the mask, 8 bytes of labels per node and the counters
+    // the mask needs the FP64 bonds (host input), the field scratch, the
+    // mask, 8 bytes of labels per node and the counters
     const size_t n = (size_t)(p->nx * p->ny * p->nz);
     auto a256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const bool copy_g = p->mem == RN_MEM_HOST;
-    const size_t off_g = 0, off_P = off_g + a256(copy_g ? 8 * p->dim * n : 0), off_dl = off_P + a256(8 * n),
-                 off_mask = off_dl + a256(8 * n), off_lab = off_mask + a256(n), off_cnt = off_lab + a256(8 * n),
-                 total = off_cnt + 256;
+    const size_t off_g = 0, off_P = off_g + a256(copy_g ? 8 * p->dim * n : 0), off_mask = off_P + a256(8 * n),
+                 off_lab = off_mask + a256(n), off_cnt = off_lab + a256(8 * n), total = off_cnt + 256;
     hipError_t he;
     char *base = (char *)ctx->pool.alloc(total, &he);
     if (!base) return RN_ENOMEM;
@@ -484,8 +483,7 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
     if (hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (!copy_g && launch_validate(lat, gd, cnt + 1, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (launch_mask(lat, gd, (int *)(base + off_lab), (unsigned *)(base + off_lab + 4 * n),
-                    (uint8_t *)(base + off_mask), (double *)(base + off_dl), (double *)(base + off_P), cnt,
-                    ctx->stream) != hipSuccess)
+                    (uint8_t *)(base + off_mask), (double *)(base + off_P), cnt, ctx->stream) != hipSuccess)
         return done(RN_EDEVICE);
     if (hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return done(RN_EDEVICE);

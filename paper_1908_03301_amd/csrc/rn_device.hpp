@@ -68,9 +68,10 @@ inline size_t ticket_bytes(int groups) { return (size_t)(groups + 1) * kTicketSt
 constexpr int kBlock = 256;      // threads per workgroup of every kernel here
 constexpr int kWave = 64;
 
+// CG state of one parity: z = D^-1 r, the direction p and u = D^-1 A p.
 template <typename T>
 struct VecSet {
-    T *r, *p, *q;
+    T *z, *p, *u;
 };
 
 // Arguments of the pass kernel (2D and 3D share the layout). Every working
@@ -91,9 +92,12 @@ struct PassArgs {
     double *P[2];                // full FP64 pressure field: CG passes after refresh m add their
                                  // step to P[m%2] in place; refresh m reads P[m%2], writes P[(m+1)%2]
     // inner-precision CG state
-    const T *gT[3];              // conductances in the inner precision (0 past the lattice edge;
-                                 // the wrap bond on the last plane of a periodic direction)
-    const T *invd;               // Jacobi preconditioner 1/d_i on live nodes, 0 elsewhere
+    const T *gT[3];              // conductances in the inner precision: 0 past the lattice edge
+                                 // (the wrap bond on the last plane of a periodic direction) and
+                                 // 0 where either end is an interior node off the live set, so
+                                 // the sum of a node's bonds is its Jacobi diagonal d_i, > 0
+                                 // exactly on live and face nodes
+    const uint8_t *mask;         // mask byte per node (3 = live)
     VecSet<T> src, dst;
     // reduction
     double *partials;            // [grid][kRed]
@@ -110,10 +114,10 @@ struct Lat {
 // launchers (rn_kernels.hip)
 hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long long *bad, hipStream_t st);
 hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
-                       double *dlive, double *P, unsigned long long *n_live, hipStream_t st);
+                       double *P, unsigned long long *n_live, hipStream_t st);
 template <typename T>
-hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dlive, T *const gT[3], T *invd,
-                        T *vec, int64_t nvec, hipStream_t st);
+hipError_t launch_scale(const Lat &L, const double *const g[3], const uint8_t *mask, T *const gT[3], T *vec,
+                        int64_t nvec, hipStream_t st);
 hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
 // One pass of every network in the block table blk[0..nblocks): entry
 // (network, local block); tab[2 * network + parity] are that network's

@@ -177,11 +177,9 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     };
     L.off_g64 = take(L.copy_g ? (size_t)8 * L.dim * n : 0);
     L.off_P = take(16 * n);
-    L.off_dl = take(8 * n);
     L.off_mask = take(n);
     L.off_gT = take((size_t)L.s * L.dim * n);
-    L.off_invd = take((size_t)L.s * n);
-    L.off_vec = take((size_t)6 * L.s * n);   // two sets of r, p, q; labels (8 bytes/node) alias here
+    L.off_vec = take((size_t)6 * L.s * n);   // two sets of z, p, u; labels (8 bytes/node) alias here
     L.off_part = take((size_t)L.grid * kRed * 8);
     L.off_tk = take(ticket_bytes(L.groups));
     L.off_cnt = take(4 * sizeof(unsigned long long));
@@ -342,8 +340,8 @@ int Engine::prepare(Net *net, hipStream_t st, std::string *err)
     if (!L.copy_g) ENG_TRY(launch_validate(lat, net->gd, cnt + 1, st));
     int *parent = (int *)(base + L.off_vec);
     unsigned *flags = (unsigned *)(base + L.off_vec + 4 * n);
-    ENG_TRY(launch_mask(lat, net->gd, parent, flags, (uint8_t *)(base + L.off_mask), (double *)(base + L.off_dl),
-                        (double *)(base + L.off_P), cnt, st));
+    ENG_TRY(launch_mask(lat, net->gd, parent, flags, (uint8_t *)(base + L.off_mask), (double *)(base + L.off_P),
+                        cnt, st));
     if (net->na == 2) ENG_TRY(launch_direct_flux(lat, net->gd[p->axis], (double *)(cnt + 2), st));
     ENG_TRY(hipEventRecord(net->ev_b, st));
     ENG_TRY(hipMemcpyAsync(h_cnt_ + 4 * net->slot, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -384,7 +382,7 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         }
         A.P[0] = (double *)(base + L.off_P);
         A.P[1] = A.P[0] + n;
-        A.invd = (const T *)(base + L.off_invd);
+        A.mask = (const uint8_t *)(base + L.off_mask);
         A.src = k == 0 ? s0 : s1;
         A.dst = k == 0 ? s1 : s0;
         A.partials = (double *)(base + L.off_part);
@@ -456,16 +454,16 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
     if (L.s == 4) {
         float *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (float *)(base + L.off_gT) + (size_t)k * n;
-        ENG_TRY(launch_scale<float>(lat, net->gd, (const double *)(base + L.off_dl), gT,
-                                    (float *)(base + L.off_invd), (float *)(base + L.off_vec), (int64_t)(6 * n), st));
+        ENG_TRY(launch_scale<float>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
+                                    (float *)(base + L.off_vec), (int64_t)(6 * n), st));
         fill_args<float>(h_tabf_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabf_ + 2 * slot, h_tabf_ + 2 * slot, 2 * sizeof(PassArgs<float>),
                                hipMemcpyHostToDevice, st));
     } else {
         double *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (double *)(base + L.off_gT) + (size_t)k * n;
-        ENG_TRY(launch_scale<double>(lat, net->gd, (const double *)(base + L.off_dl), gT,
-                                     (double *)(base + L.off_invd), (double *)(base + L.off_vec), (int64_t)(6 * n), st));
+        ENG_TRY(launch_scale<double>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
+                                     (double *)(base + L.off_vec), (int64_t)(6 * n), st));
         fill_args<double>(h_tabd_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabd_ + 2 * slot, h_tabd_ + 2 * slot, 2 * sizeof(PassArgs<double>),
                                hipMemcpyHostToDevice, st));

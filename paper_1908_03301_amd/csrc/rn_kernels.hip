@@ -8,18 +8,24 @@
 // keeps the FP32 operator spectrally within (1 +- 2^-24) of the FP64 one
 // (Rayleigh quotient sum g (x_i - x_j)^2), whatever the condition number.
 //
-// One pass per CG iteration k (single global reduction):
-//     r_k = r_{k-1} - a q_{k-1};  P += sigma a p_{k-1} (FP64);  z_k = r_k / d
-//     p_k = z_k + b p_{k-1};      q_k = A p_k     (5/7-point stencil, p_k recomputed at the halo)
-//     sums p.q, z.q, q.D^-1 q, r.z, r.r in FP64
+// One pass per CG iteration k (single global reduction). The state is kept
+// preconditioned: z = D^-1 r and u = D^-1 q, so that the halo needs no
+// diagonal:
+//     z_k = z_{k-1} - a u_{k-1};  P += sigma a p_{k-1} (FP64);  p_k = z_k + b p_{k-1}
+//     q_k = A p_k (5/7-point stencil, p_k recomputed at the halo);  u_k = q_k / d
+//     sums p.q, z.q, q.u (= q.D^-1 q), d z.z (= r.z) in FP64
 // and a = (r.z)/(p.q), r_{k+1}.z_{k+1} = r.z - 2a z.q + a^2 q.D^-1 q give the
-// next step without a second reduction. The solution is accumulated straight
-// into the FP64 pressure field every pass: an FP32 accumulator would round the
+// next step without a second reduction. d_i is recomputed in every pass as the
+// sum of the node's bonds in the inner precision (in a fixed order, the same
+// in the refresh): setup zeroes every bond that touches an interior node off
+// the live set, so d > 0 exactly on live and face nodes, and face nodes are
+// told apart by their coordinate. The solution is accumulated straight into
+// the FP64 pressure field every pass: an FP32 accumulator would round the
 // correction by 2^-24 of its size, i.e. a residual error of order 2^-24 times
 // the condition number at every refresh. Nodes outside the live set hold
-// r = p = q = 0 and 1/d = 0, so the same arithmetic keeps them at zero; they
-// are read and stored like the others so that cache lines move whole. r, p, q
-// are double-buffered because neighbours read them from the previous pass.
+// z = p = u = 0, so the same arithmetic keeps them at zero; they are read and
+// stored like the others so that cache lines move whole. z, p, u are
+// double-buffered because neighbours read them from the previous pass.
 //
 // The same kernel, in refresh mode, evaluates the FP64 true residual b - A x
 // of the pressure field with the original conductances, the face fluxes and
@@ -62,7 +68,28 @@ __device__ __forceinline__ int xcd_remap(int b, int grid)
     return (b & 7) * per + (b >> 3);
 }
 
-// Scalar update after a CG pass. t = (p.q, z.q, q.D^-1 q, r.z, r.r).
+// Jacobi diagonal of a node from its bonds to -x, +x, -y, +y (and -z, +z),
+// summed in this fixed order so that the pass and the refresh round it the
+// same way.
+template <typename T>
+__device__ __forceinline__ T diag_sum(T gxm, T gxp, T gym, T gyp)
+{
+    return (gxm + gxp) + (gym + gyp);
+}
+
+template <typename T>
+__device__ __forceinline__ T diag_sum(T gxm, T gxp, T gym, T gyp, T gzm, T gzp)
+{
+    return ((gxm + gxp) + (gym + gyp)) + (gzm + gzp);
+}
+
+// Jacobi scaling v / d. FP32: the hardware reciprocal (about 1 ulp, and a
+// fixed function of d, so the preconditioner stays one fixed diagonal) in
+// place of the much longer correctly rounded division; FP64: the division.
+__device__ __forceinline__ float jscale(float v, float d) { return v * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double jscale(double v, double d) { return v / d; }
+
+// Scalar update after a CG pass. t = (p.q, z.q, q.D^-1 q, r.z, 0).
 __device__ void step_after_cg(Scalars *s, const double *t)
 {
     const double pq = t[0], zq = t[1], qq = t[2], rz = t[3];
@@ -250,7 +277,10 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
 // ---------------------------------------------------------------- refresh (FP64)
 // Node-local FP64 work of a refresh pass. The pending step sa p (sa = sigma a)
 // is added on the fly to every pressure the stencil reads; p is zero off the
-// live set, so Ps + sa p is the updated field everywhere.
+// live set, so Ps + sa p is the updated field everywhere. Every load of the
+// node is issued before any branch on loaded data (a missing neighbour reads
+// the node itself and is dropped by a select), so a node costs one memory
+// round trip.
 template <typename T, int DIM>
 __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
                                              double *__restrict__ Pd, int x, int y, int z, double sa,
@@ -258,48 +288,71 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 {
     const int64_t sx = 1, sy = a.nx, sz = (int64_t)a.nx * a.ny;
     const int64_t i = x + sy * y + sz * z;
-    const double di = (double)a.invd[i];
-    if (di == 0.0) {
-        Pd[i] = Ps[i];
-        return;
-    }
-    // bonly: evaluate b = b - A 0, the interior pressures taken as 0 and the
-    // inlet face at 1 (the first refresh of a solve)
-    auto pn = [&](int64_t j) -> double { return Ps[j] + sa * (double)a.src.p[j]; };
-    const double pi = bonly ? 0.0 : pn(i);
-    double r64 = 0.0, qin = 0.0, qout = 0.0;
     const int c[3] = {x, y, z};
     const int n[3] = {a.nx, a.ny, a.nz};
     const int64_t st[3] = {sx, sy, sz};
+    const bool live = a.mask[i] == 3;
+    const double Pi = Ps[i];
+    const T pi_ = a.src.p[i];
+    bool has[2 * DIM];
+    T gb[2 * DIM];
+    double gd[2 * DIM], Pn[2 * DIM];
+    T pn_[2 * DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const bool wk = (a.wrap >> k) & 1;       // never the flow axis
         const int64_t span = (int64_t)(n[k] - 1) * st[k];
-        if (c[k] > 0 || wk) {
-            const int64_t j = c[k] > 0 ? i - st[k] : i + span;
-            const double g = a.g64[k][j];
-            if (g != 0.0) {
-                const bool inlet = k == a.axis && c[k] == 1;
-                r64 += g * ((bonly ? (inlet ? 1.0 : 0.0) : pn(j)) - pi);
-                if (inlet) qin += g * (1.0 - pi);
-            }
+        has[2 * k] = c[k] > 0 || wk;
+        has[2 * k + 1] = c[k] + 1 < n[k] || wk;
+        const int64_t jm = c[k] > 0 ? i - st[k] : (wk ? i + span : i);
+        const int64_t jp = c[k] + 1 < n[k] ? i + st[k] : (wk ? i - span : i);
+        const T gbm = a.gT[k][jm], gbp = a.gT[k][i];
+        const double gdm = a.g64[k][jm], gdp = a.g64[k][i];
+        gb[2 * k] = has[2 * k] ? gbm : T(0);
+        gb[2 * k + 1] = gbp;                     // 0 past the lattice edge
+        gd[2 * k] = has[2 * k] ? gdm : 0.0;
+        gd[2 * k + 1] = has[2 * k + 1] ? gdp : 0.0;
+        Pn[2 * k] = Ps[jm];
+        Pn[2 * k + 1] = Ps[jp];
+        pn_[2 * k] = a.src.p[jm];
+        pn_[2 * k + 1] = a.src.p[jp];
+    }
+    if (!live) {
+        Pd[i] = Pi;
+        return;
+    }
+    // bonly: evaluate b = b - A 0, the interior pressures taken as 0 and the
+    // inlet face at 1 (the first refresh of a solve)
+    const double pi = bonly ? 0.0 : Pi + sa * (double)pi_;
+    double r64 = 0.0, qin = 0.0, qout = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const double gm = gd[2 * k], gp = gd[2 * k + 1];
+        const double pm = Pn[2 * k] + sa * (double)pn_[2 * k];
+        const double pp = Pn[2 * k + 1] + sa * (double)pn_[2 * k + 1];
+        if (gm != 0.0) {
+            const bool inlet = k == a.axis && c[k] == 1;
+            r64 += gm * ((bonly ? (inlet ? 1.0 : 0.0) : pm) - pi);
+            if (inlet) qin += gm * (1.0 - pi);
         }
-        if (c[k] + 1 < n[k] || wk) {
-            const int64_t j = c[k] + 1 < n[k] ? i + st[k] : i - span;
-            const double g = a.g64[k][i];
-            if (g != 0.0) {
-                r64 += g * ((bonly ? 0.0 : pn(j)) - pi);
-                if (k == a.axis && c[k] == n[k] - 2) qout += g * pi;
-            }
+        if (gp != 0.0) {
+            r64 += gp * ((bonly ? 0.0 : pp) - pi);
+            if (k == a.axis && c[k] == n[k] - 2) qout += gp * pi;
         }
     }
+    // the inner diagonal, exactly as the CG pass forms it (> 0 on a live
+    // node unless its bonds underflow the inner precision)
+    T dT;
+    if constexpr (DIM == 2) dT = diag_sum(gb[0], gb[1], gb[2], gb[3]);
+    else dT = diag_sum(gb[0], gb[1], gb[2], gb[3], gb[4], gb[5]);
     const T rs = (T)(r64 / sigma_next);
-    Pd[i] = bonly ? Ps[i] : pi;
-    a.dst.r[i] = rs;
-    a.dst.p[i] = a.src.p[i];
-    a.dst.q[i] = T(0);
+    const T zs = dT > T(0) ? jscale(rs, dT) : T(0);
+    Pd[i] = bonly ? Pi : pi;
+    a.dst.z[i] = zs;
+    a.dst.p[i] = pi_;
+    a.dst.u[i] = T(0);
     acc[0] += r64 * r64;
-    acc[1] += (double)rs * (double)rs * di;
+    acc[1] += (double)rs * (double)zs;
     acc[2] += pi * r64;
     acc[3] += qin;
     acc[4] += qout;
@@ -363,18 +416,17 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         lv[sg] = xm >= 0;
         xc[sg] = lv[sg] ? xm : nx - 1;
     }
-    const T *__restrict__ rs = a.src.r;
-    const T *__restrict__ qs = a.src.q;
+    const T *__restrict__ zs = a.src.z;
+    const T *__restrict__ us = a.src.u;
     const T *__restrict__ ps = a.src.p;
-    const T *__restrict__ dv = a.invd;
-    T *__restrict__ rd = a.dst.r;
-    T *__restrict__ qd = a.dst.q;
+    T *__restrict__ zd = a.dst.z;
+    T *__restrict__ ud = a.dst.u;
     T *__restrict__ pd = a.dst.p;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
 
     // ---- issue every load
-    T d_[SEG][TY], r_[SEG][TY], q_[SEG][TY], p_[SEG][TY];
+    T z_[SEG][TY], u_[SEG][TY], p_[SEG][TY];
     double Pv[SEG][TY];
     T gxv[SEG][TY], gyv[SEG][TY + 1];
 #pragma unroll
@@ -383,9 +435,8 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
             const int64_t i = ro + xc[sg];
-            d_[sg][j] = dv[i];
-            r_[sg][j] = rs[i];
-            q_[sg][j] = qs[i];
+            z_[sg][j] = zs[i];
+            u_[sg][j] = us[i];
             p_[sg][j] = ps[i];
             Pv[sg][j] = P[i];
             gxv[sg][j] = gx[i];
@@ -402,9 +453,9 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         }
     }
     // the workgroup's outer halo rows: wave 0 the row above, the last wave the row below
-    T ed[SEG], er[SEG], eq[SEG], ep[SEG];
+    T ez[SEG], eu[SEG], ep[SEG];
 #pragma unroll
-    for (int sg = 0; sg < SEG; ++sg) ed[sg] = er[sg] = eq[sg] = ep[sg] = T(0);
+    for (int sg = 0; sg < SEG; ++sg) ez[sg] = eu[sg] = ep[sg] = T(0);
     if (w == 0 || w == NW - 1) {   // wave-uniform
         const int yh = w == 0 ? yb - 1 : yb + NW * TY;
         const bool hrow = rowm(yh) >= 0;
@@ -412,11 +463,10 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
             const int64_t i = ro + xc[sg];
-            const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i];
+            const T z0 = zs[i], u0 = us[i], p0 = ps[i];
             if (hrow && lv[sg]) {
-                ed[sg] = d0;
-                er[sg] = r0;
-                eq[sg] = q0;
+                ez[sg] = z0;
+                eu[sg] = u0;
                 ep[sg] = p0;
             }
         }
@@ -426,14 +476,13 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     const int hr_ = hleft ? lane : lane - (kWave - TY);
     const int hx = colm(hleft ? x0 - 1 : x0 + Tile2D<T, SHAPE>::COLS);
     const bool hok = (hleft || hright) && hx >= 0 && y0 + hr_ < ny;
-    T hd = T(0), hr = T(0), hq = T(0), hp = T(0), hg = T(0);
+    T hz = T(0), hu = T(0), hp = T(0), hg = T(0);
     {
         const int64_t i = hok ? (int64_t)(y0 + hr_) * nx + hx : 0;
-        const T d0 = dv[i], r0 = rs[i], q0 = qs[i], p0 = ps[i], g0 = gx[i];
+        const T z0 = zs[i], u0 = us[i], p0 = ps[i], g0 = gx[i];
         if (hok) {
-            hd = d0;
-            hr = r0;
-            hq = q0;
+            hz = z0;
+            hu = u0;
             hp = p0;
             hg = hleft ? g0 : T(0);        // bond (x0-1) -> x0 for lane 0 (nx-1 -> 0 when x wraps)
         }
@@ -446,7 +495,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         const bool rheld = rowm(y0 + j) >= 0;
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
-            const T v = d_[sg][j] * (r_[sg][j] - alpha * q_[sg][j]) + beta * p_[sg][j];
+            const T v = (z_[sg][j] - alpha * u_[sg][j]) + beta * p_[sg][j];
             pv[sg][j + 1] = (rheld && lv[sg]) ? v : T(0);
         }
     }
@@ -457,15 +506,16 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     }
     T hv[SEG];
 #pragma unroll
-    for (int sg = 0; sg < SEG; ++sg) hv[sg] = ed[sg] * (er[sg] - alpha * eq[sg]) + beta * ep[sg];   // zero unless held
+    for (int sg = 0; sg < SEG; ++sg) hv[sg] = (ez[sg] - alpha * eu[sg]) + beta * ep[sg];   // zero unless held
     __syncthreads();
 #pragma unroll
     for (int sg = 0; sg < SEG; ++sg) {
         pv[sg][0] = w == 0 ? hv[sg] : edge[1][w - 1][sg][lane];
         pv[sg][TY + 1] = w == NW - 1 ? hv[sg] : edge[0][w + 1][sg][lane];
     }
-    const T hpv = hd * (hr - alpha * hq) + beta * hp;    // zero when !hok
+    const T hpv = (hz - alpha * hu) + beta * hp;    // zero when !hok
 
+    const bool xaxis = a.axis == 0;
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
         const int yy = y0 + j;
@@ -474,9 +524,9 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         const T hgl = __shfl(hg, j, kWave);
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
+            const int x = x0 + kWave * sg + lane;
             const bool ok = valid[sg] && yy < ny;
-            const T dc = ok ? d_[sg][j] : T(0);
-            const T rc = ok ? r_[sg][j] - alpha * q_[sg][j] : T(0);
+            const T zc = z_[sg][j] - alpha * u_[sg][j];
             const T pc = pv[sg][j + 1];
             // neighbours across x: shuffles inside a segment, the neighbouring
             // segment's edge lane across a junction, the halo at the tile edges
@@ -493,24 +543,26 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             if (lane == kWave - 1) pr = rj;
             T qv = gxl * (pc - pl) + gxv[sg][j] * (pc - pr) + gyv[sg][j] * (pc - pv[sg][j]) +
                    gyv[sg][j + 1] * (pc - pv[sg][j + 2]);
-            if (dc == T(0)) qv = T(0);
+            const T d = diag_sum(gxl, gxv[sg][j], gyv[sg][j], gyv[sg][j + 1]);
+            const bool face = xaxis ? (x == 0 || x == nx - 1) : (yy == 0 || yy == ny - 1);
+            const bool live = ok && d > T(0) && !face;
+            if (!live) qv = T(0);
+            const T uv = live ? jscale(qv, d) : T(0);
             // every in-lattice node is stored (zeros and unchanged pressures off the
             // live set) so that cache lines are written whole
             if (ok) {
-                const int64_t i = (int64_t)yy * nx + x0 + kWave * sg + lane;
+                const int64_t i = (int64_t)yy * nx + x;
                 P[i] = Pv[sg][j] + sa * (double)p_[sg][j];
-                rd[i] = rc;
+                zd[i] = zc;
                 pd[i] = pc;
-                qd[i] = qv;
+                ud[i] = uv;
             }
-            const double dq = (double)qv;
-            const double dp = (double)pc, dr = (double)rc;
-            const double dd = (double)dc, dz = dd * dr;
+            const double dq = (double)qv, du = (double)uv;
+            const double dp = (double)pc, dz = live ? (double)zc : 0.0;
             acc[0] += dp * dq;
             acc[1] += dz * dq;
-            acc[2] += dq * dq * dd;
-            acc[3] += dr * dz;
-            acc[4] += dr * dr;
+            acc[2] += dq * du;
+            acc[3] += (double)d * dz * dz;
         }
     }
 }
@@ -580,9 +632,9 @@ constexpr int kRows = kTY / (kBlock / kWave);
 
 template <typename T>
 struct Raw3 {                  // one plane's loads for this thread
-    T d[kRows], r[kRows], q[kRows], p[kRows];
+    T z[kRows], u[kRows], p[kRows];
     double P[kRows];
-    T hd, hr, hq, hp;          // halo-ring node of this thread (if any)
+    T hz, hu, hp;              // halo-ring node of this thread (if any)
 };
 
 template <typename T>
@@ -613,12 +665,11 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const int xm = colm(x);
     const bool xl = xm >= 0;           // holds a column (its own or an image)
     const int xc = xl ? xm : nx - 1;
-    const T *__restrict__ rs = a.src.r;
-    const T *__restrict__ qs = a.src.q;
+    const T *__restrict__ zs = a.src.z;
+    const T *__restrict__ us = a.src.u;
     const T *__restrict__ ps = a.src.p;
-    const T *__restrict__ dv = a.invd;
-    T *__restrict__ rd = a.dst.r;
-    T *__restrict__ qd = a.dst.q;
+    T *__restrict__ zd = a.dst.z;
+    T *__restrict__ ud = a.dst.u;
     T *__restrict__ pd = a.dst.p;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
@@ -662,17 +713,15 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const int64_t i = rowoff[j] + zo;
-            R.d[j] = dv[i];
-            R.r[j] = rs[i];
-            R.q[j] = qs[i];
+            R.z[j] = zs[i];
+            R.u[j] = us[i];
             R.p[j] = ps[i];
             R.P[j] = P[i];
         }
         if (ring) {
             const int64_t i = hoff + zo;
-            R.hd = dv[i];
-            R.hr = rs[i];
-            R.hq = qs[i];
+            R.hz = zs[i];
+            R.hu = us[i];
             R.hp = ps[i];
         }
     };
@@ -689,11 +738,12 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         G.xh = xhok ? xh : T(0);           // no bond left of x = 0
         G.yh = yhok ? yh : T(0);           // no bond below y = 0
     };
-    auto pprime = [&](T d, T r, T q, T p) { return d * (r - alpha * q) + beta * p; };
+    auto pprime = [&](T z, T u, T p) { return (z - alpha * u) + beta * p; };
+    // face planes of the flow axis (z = 0 and z = nz - 1 when the flow is along z)
+    const int ax = a.axis;
 
     T pm[kRows], pc[kRows], pn[kRows];   // p' of planes zc-1, zc, zc+1 (own rows)
-    T rc[kRows], dc[kRows];              // r' and 1/d of plane zc
-    T rn[kRows], dn[kRows];              // r' and 1/d of plane zc+1
+    T zvc[kRows], zvn[kRows];            // z' of planes zc and zc+1
     T gzm[kRows];                        // gz of the bond (zc-1) -> zc
     Raw3<T> R;
     Bond3<T> Gc, Gn;
@@ -703,7 +753,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         const bool in = plm(z0 - 1) >= 0;
         load_raw(R, z0 - 1, false);
 #pragma unroll
-        for (int j = 0; j < kRows; ++j) pm[j] = (in && lok[j]) ? pprime(R.d[j], R.r[j], R.q[j], R.p[j]) : T(0);
+        for (int j = 0; j < kRows; ++j) pm[j] = (in && lok[j]) ? pprime(R.z[j], R.u[j], R.p[j]) : T(0);
         load_raw(R, z0, true);
         load_bonds(Gc, z0);
 #pragma unroll
@@ -711,18 +761,17 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const bool ok = rok[j];
-            const T r_ = R.r[j] - alpha * R.q[j];
-            pc[j] = lok[j] ? R.d[j] * r_ + beta * R.p[j] : T(0);
-            rc[j] = ok ? r_ : T(0);
-            dc[j] = ok ? R.d[j] : T(0);
+            const T z_ = R.z[j] - alpha * R.u[j];
+            pc[j] = lok[j] ? z_ + beta * R.p[j] : T(0);
+            zvc[j] = ok ? z_ : T(0);
             if (ok) {
                 const int64_t i = rowoff[j] + (int64_t)z0 * sz;
                 P[i] = R.P[j] + sa * (double)R.p[j];
-                rd[i] = r_;
+                zd[i] = z_;
             }
             lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
         }
-        if (hrow >= 0) lp[z0 % 3][hrow][hcol] = hok ? pprime(R.hd, R.hr, R.hq, R.hp) : T(0);
+        if (hrow >= 0) lp[z0 % 3][hrow][hcol] = hok ? pprime(R.hz, R.hu, R.hp) : T(0);
         load_raw(R, z0 + 1, z0 + 1 < z1);
     }
 
@@ -735,18 +784,17 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const bool ok = rok[j] && nlat;
-            const T r_ = R.r[j] - alpha * R.q[j];
-            pn[j] = (lok[j] && nheld) ? R.d[j] * r_ + beta * R.p[j] : T(0);
-            rn[j] = ok ? r_ : T(0);
-            dn[j] = ok ? R.d[j] : T(0);
+            const T z_ = R.z[j] - alpha * R.u[j];
+            pn[j] = (lok[j] && nheld) ? z_ + beta * R.p[j] : T(0);
+            zvn[j] = ok ? z_ : T(0);
             if (ok && nin) {
                 const int64_t i = rowoff[j] + (int64_t)zn * sz;
                 P[i] = R.P[j] + sa * (double)R.p[j];
-                rd[i] = r_;
+                zd[i] = z_;
             }
             if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];
         }
-        if (nin && hrow >= 0) lp[zn % 3][hrow][hcol] = hok ? pprime(R.hd, R.hr, R.hq, R.hp) : T(0);
+        if (nin && hrow >= 0) lp[zn % 3][hrow][hcol] = hok ? pprime(R.hz, R.hu, R.hp) : T(0);
         // (b) loads for the next iteration
         if (zn + 1 <= z1) load_raw(R, zn + 1, zn + 1 < z1);
         if (nin) load_bonds(Gn, zn);
@@ -764,19 +812,24 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             T qv = gxl * (p0 - lp[b][ly][lane]) + Gc.x[j] * (p0 - lp[b][ly][lane + 2]) +
                    gyl * (p0 - lp[b][ly - 1][1 + lane]) + Gc.y[j] * (p0 - lp[b][ly + 1][1 + lane]) +
                    gzm[j] * (p0 - pm[j]) + Gc.z[j] * (p0 - pn[j]);
-            if (dc[j] == T(0)) qv = T(0);
+            const T d = diag_sum(gxl, Gc.x[j], gyl, Gc.y[j], gzm[j], Gc.z[j]);
+            const int yy = yw + j;
+            const bool face = ax == 0 ? (x == 0 || x == nx - 1)
+                                      : (ax == 1 ? (yy == 0 || yy == ny - 1) : (zc == 0 || zc == nz - 1));
+            const bool live = rok[j] && d > T(0) && !face;
+            if (!live) qv = T(0);
+            const T uv = live ? jscale(qv, d) : T(0);
             if (rok[j]) {
                 const int64_t i = rowoff[j] + (int64_t)zc * sz;
                 pd[i] = p0;
-                qd[i] = qv;
+                ud[i] = uv;
             }
-            const double dp = (double)p0, dq = (double)qv, dr = (double)rc[j];
-            const double dd = (double)dc[j], dzv = dd * dr;
+            const double dp = (double)p0, dq = (double)qv, du = (double)uv;
+            const double dz = live ? (double)zvc[j] : 0.0;
             acc[0] += dp * dq;
-            acc[1] += dzv * dq;
-            acc[2] += dq * dq * dd;
-            acc[3] += dr * dzv;
-            acc[4] += dr * dr;
+            acc[1] += dz * dq;
+            acc[2] += dq * du;
+            acc[3] += (double)d * dz * dz;
         }
         // rotate
 #pragma unroll
@@ -784,8 +837,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             gzm[j] = rok[j] ? Gc.z[j] : T(0);
             pm[j] = pc[j];
             pc[j] = pn[j];
-            rc[j] = rn[j];
-            dc[j] = dn[j];
+            zvc[j] = zvn[j];
         }
         if (nin) Gc = Gn;
     }
@@ -961,16 +1013,12 @@ __global__ void uf_flags_kernel(Lat L, const double *ga, int *parent, unsigned *
     }
 }
 
-// Mask byte, diagonal d_i (live nodes, 0 elsewhere), initial pressure field
-// (faces 1 / 0, dead nodes 1 when tied to the inlet only, live nodes the
-// linear profile 1 - c_axis / (n_axis - 1), the CG's initial guess) and
-// the live count.
-__global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, const double *g2,
-                                  int *parent, const unsigned *flags, uint8_t *mask, double *dlive,
-                                  double *P, unsigned long long *n_live)
+// Mask byte, initial pressure field (faces 1 / 0, dead nodes 1 when tied to
+// the inlet only, live nodes the linear profile 1 - c_axis / (n_axis - 1),
+// the CG's initial guess) and the live count.
+__global__ void mask_final_kernel(Lat L, int *parent, const unsigned *flags, uint8_t *mask, double *P,
+                                  unsigned long long *n_live)
 {
-    const double *g[3] = {g0, g1, g2};
-    const int64_t st[3] = {1, L.nx, (int64_t)L.nx * L.ny};
     unsigned long long cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -978,7 +1026,7 @@ __global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, con
         coords(L, i, x, y, z);
         const int f = face_code(L, x, y, z);
         uint8_t m;
-        double s = 0.0, p0;
+        double p0;
         if (f == 1) {
             m = 5;
             p0 = 1.0;
@@ -992,45 +1040,42 @@ __global__ void mask_final_kernel(Lat L, const double *g0, const double *g1, con
                 const int ca = L.axis == 0 ? x : (L.axis == 1 ? y : z);
                 const int na = L.axis == 0 ? L.nx : (L.axis == 1 ? L.ny : L.nz);
                 p0 = 1.0 - (double)ca / (double)(na - 1);
-            }
-            if (m == 3) {
-                const int c[3] = {x, y, z};
-                const int n[3] = {L.nx, L.ny, L.nz};
-                double d = 0.0;
-                for (int k = 0; k < L.dim; ++k) {
-                    const bool wk = (L.wrap >> k) & 1;
-                    if (c[k] > 0) d += g[k][i - st[k]];
-                    else if (wk) d += g[k][i + (int64_t)(n[k] - 1) * st[k]];
-                    if (c[k] + 1 < n[k] || wk) d += g[k][i];
-                }
-                s = d;
                 ++cnt;
             }
         }
-        if (mask) mask[i] = m;
-        dlive[i] = s;
+        mask[i] = m;
         P[i] = p0;
     }
     cnt = (unsigned long long)wave_sum((double)cnt);
     if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(n_live, cnt);
 }
 
-// Conductances and Jacobi preconditioner in the inner precision, and zeroed CG state.
+// Conductances in the inner precision and zeroed CG state. A bond is kept
+// when it lies in the lattice (or is a wrap bond) and both of its ends are
+// live or face nodes (mask 3, 5 or 6): every occupied bond of a live node
+// leads to a live or face node, so a live node keeps all of its bonds and
+// their sum is its Jacobi diagonal, while a dead interior node keeps none.
 template <typename T>
-__global__ void scale_kernel(Lat L, const double *g0, const double *g1, const double *g2,
-                             const double *dlive, T *h0, T *h1, T *h2, T *invd, T *vec, int64_t nvec)
+__global__ void scale_kernel(Lat L, const double *g0, const double *g1, const double *g2, const uint8_t *mask,
+                             T *h0, T *h1, T *h2, T *vec, int64_t nvec)
 {
     const double *g[3] = {g0, g1, g2};
     T *h[3] = {h0, h1, h2};
+    const int64_t st[3] = {1, L.nx, (int64_t)L.nx * L.ny};
+    auto keep = [](uint8_t m) { return m == 3 || m >= 5; };
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
          i += (int64_t)gridDim.x * blockDim.x) {
         int x, y, z;
         coords(L, i, x, y, z);
         const int c[3] = {x, y, z};
         const int n[3] = {L.nx, L.ny, L.nz};
-        for (int k = 0; k < L.dim; ++k) h[k][i] = (c[k] + 1 < n[k] || ((L.wrap >> k) & 1)) ? (T)g[k][i] : T(0);
-        const double d = dlive[i];
-        invd[i] = d > 0.0 ? (T)(1.0 / d) : T(0);
+        const bool ki = keep(mask[i]);
+        for (int k = 0; k < L.dim; ++k) {
+            int64_t j = -1;
+            if (c[k] + 1 < n[k]) j = i + st[k];
+            else if ((L.wrap >> k) & 1) j = i - (int64_t)(n[k] - 1) * st[k];
+            h[k][i] = (j >= 0 && ki && keep(mask[j])) ? (T)g[k][i] : T(0);
+        }
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -1078,23 +1123,23 @@ hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long
 }
 
 hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
-                       double *dlive, double *P, unsigned long long *n_live, hipStream_t st)
+                       double *P, unsigned long long *n_live, hipStream_t st)
 {
     const int gr = grid_for(L.n);
     const double *g2 = L.dim == 3 ? g[2] : nullptr;
     uf_init_kernel<<<gr, kBlock, 0, st>>>(L.n, parent, flags);
     uf_union_kernel<<<gr, kBlock, 0, st>>>(L, g[0], g[1], g2, parent);
     uf_flags_kernel<<<gr, kBlock, 0, st>>>(L, g[L.axis], parent, flags);
-    mask_final_kernel<<<gr, kBlock, 0, st>>>(L, g[0], g[1], g2, parent, flags, mask, dlive, P, n_live);
+    mask_final_kernel<<<gr, kBlock, 0, st>>>(L, parent, flags, mask, P, n_live);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_scale(const Lat &L, const double *const g[3], const double *dlive, T *const gT[3], T *invd,
-                        T *vec, int64_t nvec, hipStream_t st)
+hipError_t launch_scale(const Lat &L, const double *const g[3], const uint8_t *mask, T *const gT[3], T *vec,
+                        int64_t nvec, hipStream_t st)
 {
-    scale_kernel<T><<<grid_for(L.n), kBlock, 0, st>>>(L, g[0], g[1], L.dim == 3 ? g[2] : nullptr, dlive, gT[0],
-                                                      gT[1], L.dim == 3 ? gT[2] : nullptr, invd, vec, nvec);
+    scale_kernel<T><<<grid_for(L.n), kBlock, 0, st>>>(L, g[0], g[1], L.dim == 3 ? g[2] : nullptr, mask, gT[0],
+                                                      gT[1], L.dim == 3 ? gT[2] : nullptr, vec, nvec);
     return hipGetLastError();
 }
 
@@ -1115,10 +1160,10 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
     return hipGetLastError();
 }
 
-template hipError_t launch_scale<float>(const Lat &, const double *const[3], const double *, float *const[3],
-                                        float *, float *, int64_t, hipStream_t);
-template hipError_t launch_scale<double>(const Lat &, const double *const[3], const double *, double *const[3],
-                                         double *, double *, int64_t, hipStream_t);
+template hipError_t launch_scale<float>(const Lat &, const double *const[3], const uint8_t *, float *const[3],
+                                        float *, int64_t, hipStream_t);
+template hipError_t launch_scale<double>(const Lat &, const double *const[3], const uint8_t *, double *const[3],
+                                         double *, int64_t, hipStream_t);
 template hipError_t launch_pass<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int, int,
                                        hipStream_t);
 template hipError_t launch_pass<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int, int,
