@@ -57,14 +57,16 @@ def pass_bytes(dim: int, n: int, s: int, live: int) -> dict:
     """Algorithmic HBM bytes of one pass kernel launch.
 
     CG pass: a live node reads z, p, u and dim conductance arrays (s bytes
-    each) and its FP64 pressure, and writes z, p, u and the pressure:
-    (dim + 6) s + 16 bytes; its Jacobi diagonal is the sum of the bonds it
-    reads. Refresh pass: every node copies its FP64 pressure (16 bytes) and
-    reads its dim inner-precision bonds (s each); a live node also reads dim
-    FP64 conductances and p and writes z, p, u: 8 dim + 4 s bytes more.
+    each) and writes z, p, u: (dim + 6) s bytes; its Jacobi diagonal is the
+    sum of the bonds it reads. Every other CG pass also reads the direction
+    of two passes back (s) and reads and writes the FP64 pressure (16): the
+    figure is the average of the two kinds. Refresh pass: every node copies
+    its FP64 pressure (16 bytes) and reads its dim inner-precision bonds (s
+    each); a live node also reads dim FP64 conductances and two directions
+    and writes z, p, u: 8 dim + 5 s bytes more.
     """
-    return {"cg": ((dim + 6) * s + 16) * live,
-            "refresh": (16 + dim * s) * n + (8 * dim + 4 * s) * live}
+    return {"cg": ((dim + 6) * s * 2 + 16 + s) * live // 2,
+            "refresh": (16 + dim * s) * n + (8 * dim + 5 * s) * live}
 
 
 def cpu_info() -> str:

@@ -22,12 +22,14 @@ struct Scalars {
     int32_t stop;       // finish after the pending refresh (breakdown path)
     int32_t fp32;       // inner vectors are FP32
     int32_t check;      // the pending refresh is a convergence check
-    int32_t pad0_;
+    int32_t flush;      // the next CG pass adds both pending steps to the FP64 field
     int64_t iters;      // CG passes executed
     int64_t refreshes;  // refresh passes executed
     int64_t passes;     // passes that did work
     int64_t max_iter;
     double alpha;       // step of the pending update x += alpha p, r -= alpha q
+    double alpha2;      // step of the update before it, still pending when the last CG
+                        // pass did not touch the FP64 field (else 0)
     double beta;        // p = r + beta p in the next CG pass
     double rho;         // exact r_k.z_k of the stored residual at the last CG pass
     double sigma;       // stored r, p, q are the residual / direction / A p divided by sigma
@@ -68,10 +70,12 @@ inline size_t ticket_bytes(int groups) { return (size_t)(groups + 1) * kTicketSt
 constexpr int kBlock = 256;      // threads per workgroup of every kernel here
 constexpr int kWave = 64;
 
-// CG state of one parity: z = D^-1 r, the direction p and u = D^-1 A p.
+// CG state of one parity: z = D^-1 r and u = D^-1 A p. The direction p has
+// three buffers (PassArgs::pbuf) because a pass may still need the one two
+// passes back.
 template <typename T>
 struct VecSet {
-    T *z, *p, *u;
+    T *z, *u;
 };
 
 // Arguments of the pass kernel (2D and 3D share the layout). Every working
@@ -99,6 +103,9 @@ struct PassArgs {
                                  // exactly on live and face nodes
     const uint8_t *mask;         // mask byte per node (3 = live)
     VecSet<T> src, dst;
+    T *pbuf[3];                  // direction p: the c-th pass of a solve (Scalars::passes = c)
+                                 // writes pbuf[c % 3] and reads pbuf[(c + 2) % 3], and a CG pass
+                                 // that flushes the FP64 field also pbuf[(c + 1) % 3]
     // reduction
     double *partials;            // [grid][kRed]
     unsigned *tickets;           // groups + 1 counters, kTicketStride bytes apart, zero between passes

@@ -179,7 +179,7 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.off_P = take(16 * n);
     L.off_mask = take(n);
     L.off_gT = take((size_t)L.s * L.dim * n);
-    L.off_vec = take((size_t)6 * L.s * n);   // two sets of z, p, u; labels (8 bytes/node) alias here
+    L.off_vec = take((size_t)7 * L.s * n);   // two sets of z, u and three p; labels (8 bytes/node) alias here
     L.off_part = take((size_t)L.grid * kRed * 8);
     L.off_tk = take(ticket_bytes(L.groups));
     L.off_cnt = take(4 * sizeof(unsigned long long));
@@ -358,8 +358,8 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
     char *base = net->base;
     const size_t n = (size_t)L.n;
     T *vec = (T *)(base + L.off_vec);
-    VecSet<T> s0{vec, vec + n, vec + 2 * n};
-    VecSet<T> s1{vec + 3 * n, vec + 4 * n, vec + 5 * n};
+    VecSet<T> s0{vec, vec + n};
+    VecSet<T> s1{vec + 2 * n, vec + 3 * n};
     for (int k = 0; k < 2; ++k) {
         PassArgs<T> A;
         std::memset(&A, 0, sizeof(A));
@@ -384,6 +384,7 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.P[1] = A.P[0] + n;
         A.mask = (const uint8_t *)(base + L.off_mask);
         A.src = k == 0 ? s0 : s1;
+        for (int b = 0; b < 3; ++b) A.pbuf[b] = vec + (4 + b) * n;
         A.dst = k == 0 ? s1 : s0;
         A.partials = (double *)(base + L.off_part);
         A.tickets = (unsigned *)(base + L.off_tk);
@@ -455,7 +456,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
         float *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (float *)(base + L.off_gT) + (size_t)k * n;
         ENG_TRY(launch_scale<float>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
-                                    (float *)(base + L.off_vec), (int64_t)(6 * n), st));
+                                    (float *)(base + L.off_vec), (int64_t)(7 * n), st));
         fill_args<float>(h_tabf_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabf_ + 2 * slot, h_tabf_ + 2 * slot, 2 * sizeof(PassArgs<float>),
                                hipMemcpyHostToDevice, st));
@@ -463,7 +464,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
         double *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (double *)(base + L.off_gT) + (size_t)k * n;
         ENG_TRY(launch_scale<double>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
-                                     (double *)(base + L.off_vec), (int64_t)(6 * n), st));
+                                     (double *)(base + L.off_vec), (int64_t)(7 * n), st));
         fill_args<double>(h_tabd_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabd_ + 2 * slot, h_tabd_ + 2 * slot, 2 * sizeof(PassArgs<double>),
                                hipMemcpyHostToDevice, st));

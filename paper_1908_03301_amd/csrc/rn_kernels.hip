@@ -11,8 +11,9 @@
 // One pass per CG iteration k (single global reduction). The state is kept
 // preconditioned: z = D^-1 r and u = D^-1 q, so that the halo needs no
 // diagonal:
-//     z_k = z_{k-1} - a u_{k-1};  P += sigma a p_{k-1} (FP64);  p_k = z_k + b p_{k-1}
+//     z_k = z_{k-1} - a u_{k-1};  p_k = z_k + b p_{k-1}
 //     q_k = A p_k (5/7-point stencil, p_k recomputed at the halo);  u_k = q_k / d
+//     every other pass: P += sigma a' p_{k-2} + sigma a p_{k-1} (FP64)
 //     sums p.q, z.q, q.u (= q.D^-1 q), d z.z (= r.z) in FP64
 // and a = (r.z)/(p.q), r_{k+1}.z_{k+1} = r.z - 2a z.q + a^2 q.D^-1 q give the
 // next step without a second reduction. d_i is recomputed in every pass as the
@@ -20,11 +21,13 @@
 // in the refresh): setup zeroes every bond that touches an interior node off
 // the live set, so d > 0 exactly on live and face nodes, and face nodes are
 // told apart by their coordinate. The solution is accumulated straight into
-// the FP64 pressure field every pass: an FP32 accumulator would round the
-// correction by 2^-24 of its size, i.e. a residual error of order 2^-24 times
-// the condition number at every refresh. Nodes outside the live set hold
+// the FP64 pressure field, two steps at a time from the stored directions
+// (p is triple-buffered for this), so the field is read and written every
+// other pass: an FP32 accumulator would round the correction by 2^-24 of its
+// size, i.e. a residual error of order 2^-24 times the condition number at
+// every refresh. Nodes outside the live set hold
 // z = p = u = 0, so the same arithmetic keeps them at zero; they are read and
-// stored like the others so that cache lines move whole. z, p, u are
+// stored like the others so that cache lines move whole. z and u are
 // double-buffered because neighbours read them from the previous pass.
 //
 // The same kernel, in refresh mode, evaluates the FP64 true residual b - A x
@@ -93,6 +96,10 @@ __device__ __forceinline__ double jscale(double v, double d) { return v / d; }
 __device__ void step_after_cg(Scalars *s, const double *t)
 {
     const double pq = t[0], zq = t[1], qq = t[2], rz = t[3];
+    // a pass that left the FP64 field alone leaves the step before it pending
+    const bool flushed = s->flush != 0;
+    s->alpha2 = flushed ? 0.0 : s->alpha;
+    s->flush = flushed ? 0 : 1;
     s->passes += 1;
     s->iters += 1;
     s->rho = rz;
@@ -140,6 +147,8 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
     const double rr64 = t[0], rrs = t[1];
     s->passes += 1;
     s->refreshes += 1;
+    s->alpha2 = 0.0;                             // the refresh applied every pending step
+    s->flush = 0;
     const double sigma_old = s->sigma;
     const double sigma = s->sigma_next;
     s->sigma = sigma;
@@ -274,16 +283,54 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     }
 }
 
+// What one pass does with the direction and the FP64 field, from the control
+// block: p1 holds p_{k-1}, whose step sa = sigma alpha is pending; p2 holds
+// p_{k-2}, whose step sa2 is also pending when the previous CG pass left the
+// field alone (then this CG pass flushes both); p0 receives p_k.
+template <typename T>
+struct Step {
+    const T *p1, *p2;
+    T *p0;
+    double sa, sa2;
+    bool flush;
+};
+
+template <typename T>
+__device__ __forceinline__ Step<T> make_step(const PassArgs<T> &a, const Scalars *s)
+{
+    const unsigned c = (unsigned)(s->passes % 3);
+    Step<T> k;
+    k.p1 = a.pbuf[c == 0 ? 2 : c - 1];
+    k.p2 = a.pbuf[c == 2 ? 0 : c + 1];
+    k.p0 = a.pbuf[c];
+    k.sa = s->sigma * s->alpha;
+    k.sa2 = s->sigma * s->alpha2;
+    k.flush = s->flush != 0;
+    return k;
+}
+
+// FP64 field with the pending steps added, oldest first (the order in which
+// one step per pass would have added them).
+__device__ __forceinline__ double with_steps(double P, double sa2, double p2, double sa, double p1)
+{
+    double v = P;
+    if (sa2 != 0.0) v = fma(sa2, p2, v);
+    if (sa != 0.0) v = fma(sa, p1, v);
+    return v;
+}
+
 // ---------------------------------------------------------------- refresh (FP64)
-// Node-local FP64 work of a refresh pass. The pending step sa p (sa = sigma a)
-// is added on the fly to every pressure the stencil reads; p is zero off the
-// live set, so Ps + sa p is the updated field everywhere. Every load of the
-// node is issued before any branch on loaded data (a missing neighbour reads
-// the node itself and is dropped by a select), so a node costs one memory
-// round trip.
+// Node-local FP64 work of a refresh pass. The pending steps (sa p1, and
+// sa2 p2 when the last CG pass left the field alone) are added on the fly to
+// every pressure the stencil reads; p is zero off the live set, so this is
+// the updated field everywhere. The node's loads go out in two batches (the
+// mask and bonds, then, on live nodes, the pressures and directions), each
+// issued before any branch on its data: two memory round trips per node, and
+// few enough registers that the rare refresh does not lower the occupancy of
+// the CG pass that shares its kernel.
 template <typename T, int DIM>
 __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
-                                             double *__restrict__ Pd, int x, int y, int z, double sa,
+                                             double *__restrict__ Pd, int x, int y, int z, const Step<T> &k_,
                                              double sigma_next, bool bonly, double (&acc)[kRed])
 {
     const int64_t sx = 1, sy = a.nx, sz = (int64_t)a.nx * a.ny;
@@ -291,45 +338,56 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     const int c[3] = {x, y, z};
     const int n[3] = {a.nx, a.ny, a.nz};
     const int64_t st[3] = {sx, sy, sz};
-    const bool live = a.mask[i] == 3;
-    const double Pi = Ps[i];
-    const T pi_ = a.src.p[i];
+    const double sa = k_.sa, sa2 = k_.sa2;
+    // neighbour j of the -k / +k bond (the node itself where there is none)
+    int64_t jn[2 * DIM];
     bool has[2 * DIM];
-    T gb[2 * DIM];
-    double gd[2 * DIM], Pn[2 * DIM];
-    T pn_[2 * DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const bool wk = (a.wrap >> k) & 1;       // never the flow axis
         const int64_t span = (int64_t)(n[k] - 1) * st[k];
         has[2 * k] = c[k] > 0 || wk;
         has[2 * k + 1] = c[k] + 1 < n[k] || wk;
-        const int64_t jm = c[k] > 0 ? i - st[k] : (wk ? i + span : i);
-        const int64_t jp = c[k] + 1 < n[k] ? i + st[k] : (wk ? i - span : i);
-        const T gbm = a.gT[k][jm], gbp = a.gT[k][i];
-        const double gdm = a.g64[k][jm], gdp = a.g64[k][i];
+        jn[2 * k] = c[k] > 0 ? i - st[k] : (wk ? i + span : i);
+        jn[2 * k + 1] = c[k] + 1 < n[k] ? i + st[k] : (wk ? i - span : i);
+    }
+    // batch 1: mask and bonds
+    const bool live = a.mask[i] == 3;
+    T gb[2 * DIM];
+    double gd[2 * DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        const T gbm = a.gT[k][jn[2 * k]], gbp = a.gT[k][i];
+        const double gdm = a.g64[k][jn[2 * k]], gdp = a.g64[k][i];
         gb[2 * k] = has[2 * k] ? gbm : T(0);
         gb[2 * k + 1] = gbp;                     // 0 past the lattice edge
         gd[2 * k] = has[2 * k] ? gdm : 0.0;
         gd[2 * k + 1] = has[2 * k + 1] ? gdp : 0.0;
-        Pn[2 * k] = Ps[jm];
-        Pn[2 * k + 1] = Ps[jp];
-        pn_[2 * k] = a.src.p[jm];
-        pn_[2 * k + 1] = a.src.p[jp];
     }
     if (!live) {
-        Pd[i] = Pi;
+        Pd[i] = Ps[i];
         return;
+    }
+    // batch 2: the node's and its neighbours' pressures and directions
+    const double Pi = Ps[i];
+    const T pi_ = k_.p1[i], pi2_ = k_.p2[i];
+    double Pn[2 * DIM];
+    T pn_[2 * DIM], pn2_[2 * DIM];
+#pragma unroll
+    for (int e = 0; e < 2 * DIM; ++e) {
+        Pn[e] = Ps[jn[e]];
+        pn_[e] = k_.p1[jn[e]];
+        pn2_[e] = k_.p2[jn[e]];
     }
     // bonly: evaluate b = b - A 0, the interior pressures taken as 0 and the
     // inlet face at 1 (the first refresh of a solve)
-    const double pi = bonly ? 0.0 : Pi + sa * (double)pi_;
+    const double pi = bonly ? 0.0 : with_steps(Pi, sa2, (double)pi2_, sa, (double)pi_);
     double r64 = 0.0, qin = 0.0, qout = 0.0;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
         const double gm = gd[2 * k], gp = gd[2 * k + 1];
-        const double pm = Pn[2 * k] + sa * (double)pn_[2 * k];
-        const double pp = Pn[2 * k + 1] + sa * (double)pn_[2 * k + 1];
+        const double pm = with_steps(Pn[2 * k], sa2, (double)pn2_[2 * k], sa, (double)pn_[2 * k]);
+        const double pp = with_steps(Pn[2 * k + 1], sa2, (double)pn2_[2 * k + 1], sa, (double)pn_[2 * k + 1]);
         if (gm != 0.0) {
             const bool inlet = k == a.axis && c[k] == 1;
             r64 += gm * ((bonly ? (inlet ? 1.0 : 0.0) : pm) - pi);
@@ -349,7 +407,7 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     const T zs = dT > T(0) ? jscale(rs, dT) : T(0);
     Pd[i] = bonly ? Pi : pi;
     a.dst.z[i] = zs;
-    a.dst.p[i] = pi_;
+    k_.p0[i] = pi_;
     a.dst.u[i] = T(0);
     acc[0] += r64 * r64;
     acc[1] += (double)rs * (double)zs;
@@ -387,7 +445,7 @@ struct Tile2D {
 
 template <typename T, int SHAPE>
 __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int yb, int lane,
-                                          int w, T alpha, T beta, double sa, double (&acc)[kRed])
+                                          int w, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
     constexpr int TY = Tile2D<T, SHAPE>::TY;
     constexpr int SEG = Tile2D<T, SHAPE>::SEG;
@@ -418,16 +476,36 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     }
     const T *__restrict__ zs = a.src.z;
     const T *__restrict__ us = a.src.u;
-    const T *__restrict__ ps = a.src.p;
+    const T *__restrict__ ps = k.p1;
+    const T *__restrict__ p2s = k.p2;
     T *__restrict__ zd = a.dst.z;
     T *__restrict__ ud = a.dst.u;
-    T *__restrict__ pd = a.dst.p;
+    T *__restrict__ pd = k.p0;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
+    const bool flush = k.flush;        // uniform: this pass adds the pending steps to P
+
+    // ---- the FP64 field (every other pass). It does not depend on the
+    // stencil: with FP32 vectors it is updated first, which frees its
+    // registers for the rest of the tile (measured faster on the FP32 pass);
+    // with FP64 vectors its loads join the tile's and it is stored at the end
+    // (measured faster there).
+    constexpr bool kFieldFirst = sizeof(T) == 4;
+    if (kFieldFirst && flush) {
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int yy = y0 + j;
+#pragma unroll
+            for (int sg = 0; sg < SEG; ++sg) {
+                const int64_t i = (int64_t)rowc(yy) * nx + xc[sg];
+                const double v = with_steps(P[i], k.sa2, (double)p2s[i], k.sa, (double)ps[i]);
+                if (valid[sg] && yy < ny) P[i] = v;
+            }
+        }
+    }
 
     // ---- issue every load
     T z_[SEG][TY], u_[SEG][TY], p_[SEG][TY];
-    double Pv[SEG][TY];
     T gxv[SEG][TY], gyv[SEG][TY + 1];
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
@@ -438,9 +516,22 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             z_[sg][j] = zs[i];
             u_[sg][j] = us[i];
             p_[sg][j] = ps[i];
-            Pv[sg][j] = P[i];
             gxv[sg][j] = gx[i];
             gyv[sg][j + 1] = gy[i];
+        }
+    }
+    double Pv[SEG][TY];
+    T p2_[SEG][TY];
+    if (!kFieldFirst && flush) {
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int64_t ro = (int64_t)rowc(y0 + j) * nx;
+#pragma unroll
+            for (int sg = 0; sg < SEG; ++sg) {
+                const int64_t i = ro + xc[sg];
+                Pv[sg][j] = P[i];
+                p2_[sg][j] = k.sa2 != 0.0 ? p2s[i] : T(0);   // none pending right after a refresh
+            }
         }
     }
     {   // bond below the wave: none at y = 0 unless y wraps (then the bond ny-1 -> 0)
@@ -552,7 +643,8 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             // live set) so that cache lines are written whole
             if (ok) {
                 const int64_t i = (int64_t)yy * nx + x;
-                P[i] = Pv[sg][j] + sa * (double)p_[sg][j];
+                if (!kFieldFirst && flush)
+                    P[i] = with_steps(Pv[sg][j], k.sa2, (double)p2_[sg][j], k.sa, (double)p_[sg][j]);
                 zd[i] = zc;
                 pd[i] = pc;
                 ud[i] = uv;
@@ -589,7 +681,28 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
     const int first = xcd_remap(lb, a.grid);     // uniform per workgroup
     const int m = (int)(s->refreshes & 1);
-    const double sa = s->sigma * s->alpha;
+    const Step<T> st = make_step(a, s);
+    if (mode != MODE_CG) {
+        // refresh: node by node over the workgroup's tiles (no LDS)
+        const double sigma_next = s->sigma_next;
+        const bool bonly = s->first == 1;
+        for (int k = 0; k < a.tpw; ++k) {
+            const int tile = first + k * a.grid;
+            if (tile >= a.ntiles) break;
+            const int tx = tile % a.ntx, ty = tile / a.ntx;
+            const int x0 = tx * Tile2D<T, SHAPE>::COLS;
+            const int y0 = ty * Tile2D<T, SHAPE>::ROWS + w * Tile2D<T, SHAPE>::TY;
+            const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
+            for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
+                const int x = x0 + kWave * sg + lane;
+                if (x < a.nx)
+                    for (int yy = y0; yy < y1; ++yy)
+                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
+            }
+        }
+        finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
+        return;
+    }
     // a workgroup takes a.tpw tiles, grid apart (each XCD keeps contiguous ranges)
     for (int k = 0; k < a.tpw; ++k) {
         const int tile = first + k * a.grid;
@@ -598,20 +711,7 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         const int x0 = tx * Tile2D<T, SHAPE>::COLS;
         const int yb = ty * Tile2D<T, SHAPE>::ROWS;
-        if (mode == MODE_CG) {
-            cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, sa, acc);
-        } else {
-            const double sigma_next = s->sigma_next;
-            const bool bonly = s->first == 1;
-            const int y0 = yb + w * Tile2D<T, SHAPE>::TY;
-            const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
-            for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
-                const int x = x0 + kWave * sg + lane;
-                if (x < a.nx)
-                    for (int yy = y0; yy < y1; ++yy)
-                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, sa, sigma_next, bonly, acc);
-            }
-        }
+        cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
     }
     finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
 }
@@ -632,7 +732,7 @@ constexpr int kRows = kTY / (kBlock / kWave);
 
 template <typename T>
 struct Raw3 {                  // one plane's loads for this thread
-    T z[kRows], u[kRows], p[kRows];
+    T z[kRows], u[kRows], p[kRows], p2[kRows];
     double P[kRows];
     T hz, hu, hp;              // halo-ring node of this thread (if any)
 };
@@ -646,7 +746,7 @@ struct Bond3 {                 // bonds of one plane for this thread's rows
 
 template <typename T>
 __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int y0, int z0,
-                                          int z1, T alpha, T beta, double sa, double (&acc)[kRed])
+                                          int z1, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
     __shared__ T lp[3][kTY + 2][kTX + 2];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -667,13 +767,16 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const int xc = xl ? xm : nx - 1;
     const T *__restrict__ zs = a.src.z;
     const T *__restrict__ us = a.src.u;
-    const T *__restrict__ ps = a.src.p;
+    const T *__restrict__ ps = k.p1;
+    const T *__restrict__ p2s = k.p2;
     T *__restrict__ zd = a.dst.z;
     T *__restrict__ ud = a.dst.u;
-    T *__restrict__ pd = a.dst.p;
+    T *__restrict__ pd = k.p0;
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
     const T *__restrict__ gz = a.gT[2];
+    const bool flush = k.flush;        // uniform: this pass adds the pending steps to P
+    const double sa = k.sa, sa2 = k.sa2;
     const int yw = y0 + w * kRows;                 // first row of this wave
     bool rok[kRows], lok[kRows];                   // lattice node / slot holding a node or an image
     int64_t rowoff[kRows];                         // clamped x + sy * y of each row
@@ -716,7 +819,14 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             R.z[j] = zs[i];
             R.u[j] = us[i];
             R.p[j] = ps[i];
-            R.P[j] = P[i];
+        }
+        if (flush && ring) {           // a plane this tile stores: its FP64 field
+#pragma unroll
+            for (int j = 0; j < kRows; ++j) {
+                const int64_t i = rowoff[j] + zo;
+                R.P[j] = P[i];
+                R.p2[j] = p2s[i];
+            }
         }
         if (ring) {
             const int64_t i = hoff + zo;
@@ -766,7 +876,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvc[j] = ok ? z_ : T(0);
             if (ok) {
                 const int64_t i = rowoff[j] + (int64_t)z0 * sz;
-                P[i] = R.P[j] + sa * (double)R.p[j];
+                if (flush) P[i] = with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]);
                 zd[i] = z_;
             }
             lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
@@ -789,7 +899,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvn[j] = ok ? z_ : T(0);
             if (ok && nin) {
                 const int64_t i = rowoff[j] + (int64_t)zn * sz;
-                P[i] = R.P[j] + sa * (double)R.p[j];
+                if (flush) P[i] = with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]);
                 zd[i] = z_;
             }
             if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];
@@ -859,7 +969,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int tile = xcd_remap(lb, a.grid);
     const int m = (int)(s->refreshes & 1);
-    const double sa = s->sigma * s->alpha;
+    const Step<T> st = make_step(a, s);
     // tile index is uniform per workgroup: idle workgroups still reach the reduction
     if (tile < a.ntiles) {
         const int tx = tile % a.ntx;
@@ -868,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
         const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
         const int z1 = min(z0 + a.tile_z, a.nz);
         if (mode == MODE_CG) {
-            cg3d_tile<T>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, sa, acc);
+            cg3d_tile<T>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, st, acc);
         } else {
             const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
             const double sigma_next = s->sigma_next;
@@ -879,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
                     const int yy = y0 + w * kRows + j;
                     if (yy >= a.ny) break;
                     for (int zz = z0; zz < z1; ++zz)
-                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, sa, sigma_next, bonly, acc);
+                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
                 }
         }
     }

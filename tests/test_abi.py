@@ -116,10 +116,10 @@ def test_footprint(lib):
     f64 = B.rn_footprint(B.problem(net), B.opts(B.RN_FP64))
     f32 = B.rn_footprint(B.problem(net), B.opts(B.RN_MIXED))
     # host input: FP64 copy of g (16) + P x2 (16) + mask (1), then in the inner
-    # precision s: dim conductance arrays and two sets of z, p, u
-    assert f64 >= n * (16 + 16 + 1 + 8 * (2 + 6))
-    assert f32 >= n * (16 + 16 + 1 + 4 * (2 + 6))
-    assert f32 < f64 < n * (16 + 16 + 1 + 8 * (2 + 6) + 2)
+    # precision s: dim conductance arrays, two sets of z, u and three of p
+    assert f64 >= n * (16 + 16 + 1 + 8 * (2 + 7))
+    assert f32 >= n * (16 + 16 + 1 + 4 * (2 + 7))
+    assert f32 < f64 < n * (16 + 16 + 1 + 8 * (2 + 7) + 2)
     assert B.rn_footprint(_prob(dim=5)) == 0
 
 
