@@ -214,6 +214,20 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
     s->check = 0;
 }
 
+// The control block is read at the start of every pass by the threads that
+// will need it at the end: thread t < kScalWords loads its 8-byte word into a
+// register, so the last workgroup's scalar step runs on an LDS copy instead of
+// waiting for a chain of memory round trips after the reduction.
+constexpr int kScalWords = (int)(sizeof(Scalars) / 8);
+static_assert(sizeof(Scalars) % 8 == 0 && kScalWords <= kBlock, "control block words");
+
+__device__ __forceinline__ unsigned long long prefetch_scalars(const Scalars *s)
+{
+    const int t = threadIdx.x < kScalWords ? (int)threadIdx.x : 0;
+    const unsigned long long v = reinterpret_cast<const unsigned long long *>(s)[t];
+    return threadIdx.x < kScalWords ? v : 0ull;
+}
+
 // Per-workgroup partials, then the last workgroup to arrive sums them in
 // block order (a fixed order, so the result does not depend on scheduling)
 // and runs the scalar update. Arrival is counted in two levels: on the counter
@@ -222,10 +236,11 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
 // after another, so a single counter for a 2048-workgroup pass queued 2048
 // atomics at the end of every pass.
 __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tickets, Scalars *s, int lb, int grid,
-                            int groups, int mode)
+                            int groups, int mode, unsigned long long spre)
 {
     __shared__ double red[kBlock / kWave][kRed];
     __shared__ int is_last;
+    __shared__ unsigned long long sl[kScalWords];
     constexpr int kStride = kTicketStride / (int)sizeof(unsigned);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
@@ -271,6 +286,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     // every workgroup has counted: clear the counters for the next pass
     if (threadIdx.x <= groups)
         __hip_atomic_store(tickets + threadIdx.x * kStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < kScalWords) sl[threadIdx.x] = spre;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t[kRed];
@@ -278,9 +294,12 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
             t[k] = 0.0;
             for (int ww = 0; ww < kBlock / kWave; ++ww) t[k] += red[ww][k];
         }
-        if (mode == MODE_CG) step_after_cg(s, t);
-        else step_after_refresh(s, t);
+        Scalars *ls = reinterpret_cast<Scalars *>(sl);
+        if (mode == MODE_CG) step_after_cg(ls, t);
+        else step_after_refresh(ls, t);
     }
+    __syncthreads();
+    if (threadIdx.x < kScalWords) reinterpret_cast<unsigned long long *>(s)[threadIdx.x] = sl[threadIdx.x];
 }
 
 // What one pass does with the direction and the FP64 field, from the control
@@ -700,9 +719,11 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
                         refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
             }
         }
-        finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
+        // (a rare pass: the control block is read here, not held through the refresh)
+        finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, prefetch_scalars(s));
         return;
     }
+    const unsigned long long spre = prefetch_scalars(s);
     // a workgroup takes a.tpw tiles, grid apart (each XCD keeps contiguous ranges)
     for (int k = 0; k < a.tpw; ++k) {
         const int tile = first + k * a.grid;
@@ -713,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
         const int yb = ty * Tile2D<T, SHAPE>::ROWS;
         cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
     }
-    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
+    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
 }
 
 // ---------------------------------------------------------------- 3D pass
@@ -964,6 +985,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
     const PassArgs<T> &a = tab[2 * e.x + parity];
     const int lb = (int)e.y;
     Scalars *s = scal + e.x;          // == a.s; indexed directly to shorten the load chain
+    const unsigned long long spre = prefetch_scalars(s);
     const int mode = s->mode;
     if (mode == MODE_DONE) return;
     double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -993,7 +1015,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
                 }
         }
     }
-    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode);
+    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
 }
 
 // ---------------------------------------------------------------- setup kernels
