@@ -101,6 +101,28 @@ def traffic_from_profiles(workload: str, precision: str):
         return None
 
 
+def copy_ceiling_gbps(mib: int = 1024) -> float:
+    """Device-to-device copy rate (read + write bytes / time) of a plain copy of
+    MIB MiB between two fresh buffers, timed with events on the current stream:
+    the practical HBM ceiling the pass kernel is compared with."""
+    import torch
+    nbytes = mib << 20
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(5):
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e9
+
+
 def run_solves(ctx, B, prob_by_axis, precision, tol, steps, warmup, max_iter=2_000_000):
     lat, results = [], []
     o = B.opts(precision, tol, max_iter=max_iter)
@@ -193,6 +215,7 @@ def main():
     value = solves / total_m
 
     # roofline of the pass kernel (mixed leg: FP32 inner passes and FP64 refreshes)
+    # (each axis has its own live set)
     n = net.n
     n_live = res_m[0][1]["n_live"]
     pb = pass_bytes(net.dim, n, 4, n_live)
@@ -200,12 +223,17 @@ def main():
     launches = sum(r["passes"] for _, r in res_m)
     iters = sum(r["iters"] for _, r in res_m)
     refr = sum(r["refreshes"] for _, r in res_m)
-    alg_bytes = iters * pb["cg"] + refr * pb["refresh"]
+    alg_bytes = sum(r["iters"] * pass_bytes(net.dim, n, 4, r["n_live"])["cg"] +
+                    r["refreshes"] * pass_bytes(net.dim, n, 4, r["n_live"])["refresh"] for _, r in res_m)
+    live_iters = sum(r["n_live"] * r["iters"] for _, r in res_m)
     avg_launch_s = loop_t / max(launches, 1)
     achieved = alg_bytes / loop_t / 1e9
     traffic = traffic_from_profiles(args.workload, "mixed")
+    copy_gbps = copy_ceiling_gbps()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "copy_ceiling": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
+                "traffic_GBps": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
                 "kernel": f"pass{net.dim}d_kernel<float>", "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "launches": launches, "cg_passes": iters, "refresh_passes": refr,
                 "bytes_per_cg_pass": pb["cg"], "bytes_per_refresh_pass": pb["refresh"]}
@@ -217,7 +245,8 @@ def main():
                       "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"},
            "latency_ms": {"p50": round(1e3 * float(np.percentile(lat_m, 50)), 3),
                           "p99": round(1e3 * float(np.percentile(lat_m, 99)), 3)},
-           "roofline": roofline}
+           "roofline": roofline,
+           "live_node_iters_per_s": round(live_iters / loop_t, 1)}
     out["results"] = {f"K_axis{ax}": r["K"] for ax, r in res_m[: len(wl["axes"])]}
     out["iters_mixed"] = {f"axis{ax}": r["iters"] for ax, r in res_m[: len(wl["axes"])]}
 
@@ -240,9 +269,9 @@ def main():
 
     if not args.no_fp64:
         lat_d, res_d = leg(B.RN_FP64)
-        pbd = pass_bytes(net.dim, n, 8, res_d[0][1]["n_live"])
         loop_d = sum(r["t_loop_s"] for _, r in res_d)
-        bytes_d = sum(r["iters"] for _, r in res_d) * pbd["cg"] + sum(r["refreshes"] for _, r in res_d) * pbd["refresh"]
+        bytes_d = sum(r["iters"] * pass_bytes(net.dim, n, 8, r["n_live"])["cg"] +
+                      r["refreshes"] * pass_bytes(net.dim, n, 8, r["n_live"])["refresh"] for _, r in res_d)
         out["fp64_cg"] = {"solves_per_s": round(len(lat_d) / sum(lat_d), 4),
                           "p50_ms": round(1e3 * float(np.percentile(lat_d, 50)), 3),
                           "p99_ms": round(1e3 * float(np.percentile(lat_d, 99)), 3),
