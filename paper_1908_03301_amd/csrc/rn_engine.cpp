@@ -152,12 +152,14 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
         // another, so a small network's pass takes as long as one tile's
         // stream, while a large one is bound by bytes, and every tile reads
         // two halo planes. Measured per pass (mixed): 32^3 24.1 / 16.4 /
-        // 12.8 us at 8 / 4 / 2 planes, 128^3 29.8 / 28.2 / 32.8 us, 192^3
-        // 92.7 / 96.9 us at 8 / 4; the 512-network batch was 5% slower with
+        // 12.8 us at 8 / 4 / 2 planes, 128^3 29.8 / 28.2 / 32.8 us; 192^3
+        // 80.5 / 76.3 us at 8 / 16; 256^3 169.1 / 164.9 us at 16 / 32 (the
+        // kernel runs 2 waves per SIMD, so 16-plane tiles of 256^3 need two
+        // rounds of workgroups); the 512-network batch was 5% slower with
         // 2-plane tiles than with 4.
         L.ntx = div_up((int)p->nx, kTX);
         L.nty = div_up((int)p->ny, kTY);
-        L.tile_z = L.n >= (int64_t)12 << 20 ? kTZ : (L.n >= (int64_t)3 << 20 ? kTZ / 2 : kTZ / 4);
+        L.tile_z = L.n >= (int64_t)12 << 20 ? 2 * kTZ : (L.n >= (int64_t)3 << 20 ? kTZ : kTZ / 4);
         L.ntz = div_up((int)p->nz, L.tile_z);
         L.ntiles = L.ntx * L.nty * L.ntz;
         L.grid = L.ntiles;

@@ -327,3 +327,24 @@ def test_full_256_stratified(ctx, oracle_mod):
         assert res.converged and c.rel_resid <= 1.01e-8
         assert res.G == pytest.approx(c.G_E, rel=1e-9)
         assert 0.0 < res.K <= bound
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("shape,axis", [((150, 151, 149), 2), ((230, 232, 229), 0)])
+def test_deep_3d_tiles_ragged(ctx, oracle_mod, shape, axis):
+    """3D networks in the two deep-tile size classes (3.4 M nodes: 16-plane
+    tiles; 12.2 M nodes: 32-plane tiles), with a ragged last tile along z and
+    a ragged tile edge in x and y. The mask is checked bit for bit against the
+    oracle's search, the oracle re-evaluates the residual of the returned
+    pressures (FP64, from the original conductances), and the energy
+    conductance matches the oracle's x.(b - A x) evaluation."""
+    nx, ny, nz = shape
+    net = I.fbm_network(3, nx, ny, nz, H=0.7, sigma=1.5, occupancy=0.6, index=911, axis=axis)
+    res, P, M = gpu_solve(ctx, net, B.RN_MIXED)
+    say(f"{shape} axis {axis}: K {res.K!r} live {res.n_live} iters {res.iters} refreshes {res.refreshes}")
+    ref_mask, nl = oracle_mod.mask_bfs(net)
+    np.testing.assert_array_equal(M, ref_mask)
+    assert res.n_live == nl
+    c = oracle_mod.check_pressure(net, P)
+    assert res.converged and c.rel_resid <= 1.01e-8
+    assert res.G == pytest.approx(c.G_E, rel=1e-9)
