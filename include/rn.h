@@ -61,7 +61,11 @@ extern "C" {
 
 /* rn_opts.precision */
 #define RN_FP64 0   /* FP64 CG throughout */
-#define RN_MIXED 1  /* FP32 inner CG, FP64 residual refresh, solution and flux */
+#define RN_MIXED 1  /* FP32 inner CG, FP64 residual refresh, solution and flux. The
+                       inner CG uses the conductances rounded to FP32: a live node whose
+                       bonds all round to 0 (below about 1e-38) is never corrected by it,
+                       and the solve then ends with RN_ENOCONV; scale such inputs, since
+                       K is linear in g. */
 
 /* rn_problem.mem */
 #define RN_MEM_HOST 0

@@ -27,12 +27,12 @@ struct Scalars {
     int64_t refreshes;  // refresh passes executed
     int64_t passes;     // passes that did work
     int64_t max_iter;
-    double alpha;       // step of the pending update x += alpha p, r -= alpha q
+    double alpha;       // step of the pending update x += alpha p, z -= alpha u
     double alpha2;      // step of the update before it, still pending when the last CG
                         // pass did not touch the FP64 field (else 0)
-    double beta;        // p = r + beta p in the next CG pass
+    double beta;        // p = z + beta p in the next CG pass
     double rho;         // exact r_k.z_k of the stored residual at the last CG pass
-    double sigma;       // stored r, p, q are the residual / direction / A p divided by sigma
+    double sigma;       // the stored state (z = D^-1 r, p, u = D^-1 A p) is scaled by 1 / sigma
     double sigma_next;  // sigma the pending refresh will use
     double rmax;        // largest stored sqrt(r.z) since the last refresh
     double tol, delta;

@@ -439,13 +439,14 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
 // A workgroup owns a tile of 64 SEG consecutive x and 4 TY rows; wave w holds
 // rows w TY .. w TY + TY - 1, each as SEG segments of 64 columns (lane l holds
 // columns x0 + 64 s + l). Every load of the tile (the rows, one halo row above
-// and below the workgroup, the halo columns, the bonds and the FP64
-// pressures) is issued up front at a clamped, in-bounds address with no
-// branch on loaded data, so the tile's whole memory traffic is in flight at
-// once; out-of-lattice values are then zeroed with selects. Rows next to
-// another wave's rows get that wave's p' through LDS (one barrier), so only 2
-// rows in 4 TY are re-read. Off the live set r = q = p = 0 in memory, so the
-// arithmetic needs no mask; only stores are restricted to the lattice.
+// and below the workgroup, the halo columns and the bonds) is issued up front
+// at a clamped, in-bounds address with no branch on loaded data, so the
+// tile's whole memory traffic is in flight at once; out-of-lattice values are
+// then zeroed with selects. Rows next to another wave's rows get that wave's
+// p' through LDS (one barrier), so only 2 rows in 4 TY are re-read. Off the
+// live set z = u = p = 0 in memory, so p' needs no mask; q is zeroed off the
+// live set, where the bond sum d is 0 (dead node) or the node is on a face;
+// only stores are restricted to the lattice.
 // x-neighbours come from lane shuffles (across a segment junction from lane 63
 // of one segment and lane 0 of the next); lanes 0..TY-1 and 64-TY..63 load the
 // halo columns x0-1 and x0+64 SEG (one row each), which shuffles hand to lane
