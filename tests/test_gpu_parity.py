@@ -274,8 +274,9 @@ def test_full_2048_fbm(ctx, oracle_mod):
 @pytest.mark.parametrize("precision", [B.RN_FP64, B.RN_MIXED])
 def test_large_ragged_several_tiles_per_workgroup(ctx, oracle_mod, precision):
     """1900 x 2000 FBM: 3,750 (FP64) or 1,875 (FP32) tiles, so workgroups run
-    2 (FP64) or 1 (FP32) tiles per pass, over a grid that does not divide the
-    tile count in FP64; checked with the oracle's mask and operator."""
+    2 tiles per pass, over a grid that does not divide the tile count (the
+    last workgroups have one tile); checked with the oracle's mask and
+    operator."""
     net = I.fbm_network(2, 1900, 2000, 1, H=0.7, sigma=1.5, occupancy=0.65, index=31)
     for axis in (0, 1):
         n2 = net.with_axis(axis)
