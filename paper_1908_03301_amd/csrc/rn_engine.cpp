@@ -124,6 +124,7 @@ double cross_section(const rn_problem *p)
 // workgroup. On the 2048^2 FP64 pass, three or four tiles per workgroup were
 // 2% slower than two.
 constexpr int kWGTarget2D = 1024, kTpwMax2D = 2, kSmall2D = 128;
+constexpr int kResident3D = 512;   // 3D workgroups resident at once (256 CUs x 2)
 
 
 Layout make_layout(const rn_problem *p, const rn_opts *o)
@@ -151,18 +152,32 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
         L.tpw = std::max(1, std::min(kTpwMax2D, div_up(L.ntiles, kWGTarget2D)));
         L.grid = div_up(L.ntiles, L.tpw);
     } else {
-        // planes per tile, by size: a tile streams its planes one after
-        // another, so a small network's pass takes as long as one tile's
-        // stream, while a large one is bound by bytes, and every tile reads
-        // two halo planes. Measured per pass (mixed): 32^3 24.1 / 16.4 /
-        // 12.8 us at 8 / 4 / 2 planes, 128^3 29.8 / 28.2 / 32.8 us; 192^3
-        // 80.5 / 76.3 us at 8 / 16; 256^3 169.1 / 164.9 us at 16 / 32 (the
-        // kernel runs 2 waves per SIMD, so 16-plane tiles of 256^3 need two
-        // rounds of workgroups); the 512-network batch was 5% slower with
-        // 2-plane tiles than with 4.
+        // planes per tile: a tile streams its planes one after another, so
+        // a small network's pass takes as long as one tile's stream, while a
+        // large one is bound by bytes. The 3D kernel runs 2 waves per SIMD,
+        // i.e. kResident3D = 512 workgroups at once; tile_z is the one that
+        // needs the fewest rounds of workgroups and, among those, gives the
+        // most tiles. Measured per mixed pass, against the tile depth this
+        // rule does not pick: 32^3 16.6 -> 12.7 us (4 -> 2 planes), 64^3
+        // 16.8 -> 13.6 us (4 -> 2), 192^3 80.5 -> 76.3 us (8 -> 16), 256^3
+        // 169.1 -> 164.9 us (16 -> 32), 256^2 x 64 48.5 -> 40.2 us (16 -> 8).
+        // A batch of 512 networks of 32^3 to 128^3 and 64^2 to 1024^2 was 5%
+        // slower with 2-plane tiles on every network below 3 M nodes.
         L.ntx = div_up((int)p->nx, kTX);
         L.nty = div_up((int)p->ny, kTY);
-        L.tile_z = L.n >= (int64_t)12 << 20 ? 2 * kTZ : (L.n >= (int64_t)3 << 20 ? kTZ : kTZ / 4);
+        {
+            int best_tz = kTZ / 8, best_rounds = 0, best_tiles = 0;
+            for (int tz = 2 * kTZ; tz >= kTZ / 8; tz /= 2) {
+                const int tiles = L.ntx * L.nty * div_up((int)p->nz, tz);
+                const int rounds = div_up(tiles, kResident3D);
+                if (best_tiles == 0 || rounds < best_rounds || (rounds == best_rounds && tiles > best_tiles)) {
+                    best_tz = tz;
+                    best_rounds = rounds;
+                    best_tiles = tiles;
+                }
+            }
+            L.tile_z = best_tz;
+        }
         L.ntz = div_up((int)p->nz, L.tile_z);
         L.ntiles = L.ntx * L.nty * L.ntz;
         L.grid = L.ntiles;

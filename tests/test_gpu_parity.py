@@ -331,11 +331,11 @@ def test_full_256_stratified(ctx, oracle_mod):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("shape,axis", [((150, 151, 149), 2), ((230, 232, 229), 0)])
+@pytest.mark.parametrize("shape,axis", [((150, 151, 149), 2), ((230, 232, 229), 0), ((250, 256, 61), 1)])
 def test_deep_3d_tiles_ragged(ctx, oracle_mod, shape, axis):
-    """3D networks in the two deep-tile size classes (3.4 M nodes: 16-plane
-    tiles; 12.2 M nodes: 32-plane tiles), with a ragged last tile along z and
-    a ragged tile edge in x and y. The mask is checked bit for bit against the
+    """3D networks whose tiles are 16 (150 x 151 x 149), 32 (230 x 232 x 229)
+    and 8 (250 x 256 x 61) planes deep, with a ragged last tile along z and a
+    ragged tile edge in x and y. The mask is checked bit for bit against the
     oracle's search, the oracle re-evaluates the residual of the returned
     pressures (FP64, from the original conductances), and the energy
     conductance matches the oracle's x.(b - A x) evaluation."""
