@@ -234,6 +234,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "copy_ceiling": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
                 "traffic_GBps": round(traffic / avg_launch_s / 1e9, 1) if traffic else None,
+                "traffic_frac": round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4) if traffic else None,
                 "kernel": f"pass{net.dim}d_kernel<float>", "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "launches": launches, "cg_passes": iters, "refresh_passes": refr,
                 "bytes_per_cg_pass": pb["cg"], "bytes_per_refresh_pass": pb["refresh"]}
