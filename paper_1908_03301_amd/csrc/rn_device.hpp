@@ -11,7 +11,8 @@ namespace rn {
 
 // Per-network control block (device memory). One pass kernel launch reads
 // mode / alpha / beta / sigma at entry; the last workgroup to finish reduces
-// the partial sums in a fixed order and writes the next mode and scalars.
+// the partial sums in a fixed order and writes the next mode and scalars. The
+// host copies the blocks to pinned memory after each chunk of launches.
 enum PassMode : int32_t { MODE_CG = 0, MODE_REFRESH = 1, MODE_DONE = 2 };
 
 struct Scalars {
@@ -45,13 +46,6 @@ struct Scalars {
     double est_check;   // predicted relative residual that triggered the pending check
     double Q_in, Q_out, xr;  // fluxes and x.(b - A x) from the last refresh
     uint32_t pad1_, pad2_;
-};
-
-// What the host polls (copied to pinned memory after each chunk of launches).
-struct Status {
-    int32_t mode, status;
-    int64_t iters, refreshes, passes;
-    double est_rel, rel_resid;
 };
 
 constexpr int kRed = 5;          // partial sums per workgroup

@@ -25,10 +25,10 @@
 // (p is triple-buffered for this), so the field is read and written every
 // other pass: an FP32 accumulator would round the correction by 2^-24 of its
 // size, i.e. a residual error of order 2^-24 times the condition number at
-// every refresh. Nodes outside the live set hold
-// z = p = u = 0, so the same arithmetic keeps them at zero; they are read and
-// stored like the others so that cache lines move whole. z and u are
-// double-buffered because neighbours read them from the previous pass.
+// every refresh. Nodes outside the live set hold z = p = u = 0, so the same
+// arithmetic keeps them at zero; they are read and stored like the others so
+// that cache lines move whole. z and u are double-buffered because
+// neighbours read them from the previous pass.
 //
 // The same kernel, in refresh mode, evaluates the FP64 true residual b - A x
 // of the pressure field with the original conductances, the face fluxes and
