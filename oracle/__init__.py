@@ -53,7 +53,7 @@ def _load():
         common = [C.c_int, i64, i64, i64, C.c_int, C.c_int, dp, dp, dp]
         lib.rno_mask_bfs.argtypes = common + [u8p, C.POINTER(i64)]
         lib.rno_mask_uf.argtypes = common + [u8p, C.POINTER(i64)]
-        lib.rno_solve.argtypes = common + [C.c_double, i64, dp, u8p, C.POINTER(_Result)]
+        lib.rno_solve.argtypes = common + [C.c_double, i64, C.c_int, C.c_int, dp, u8p, C.POINTER(_Result)]
         lib.rno_check_pressure.argtypes = common + [dp, dp]
         for f in (lib.rno_mask_bfs, lib.rno_mask_uf, lib.rno_solve, lib.rno_check_pressure):
             f.restype = C.c_int
@@ -124,14 +124,22 @@ def mask_uf(net) -> tuple:
     return out, int(nl.value)
 
 
+X0_LINEAR, X0_ZERO = 0, 1
+JACOBI, NONE = 0, 1
+
+
 def solve(net, tol: float = 1e-12, max_iter: int = 1_000_000, want_pressure: bool = True,
-          want_mask: bool = False, raise_on_error: bool = True) -> OracleResult:
-    """Jacobi-PCG to ||b - A x|| <= tol ||b|| (FP64), then fluxes, energy G and K."""
+          want_mask: bool = False, raise_on_error: bool = True, x0: int = X0_ZERO,
+          precond: int = JACOBI) -> OracleResult:
+    """Preconditioned CG to ||b - A x|| <= tol ||b|| (FP64), then fluxes, energy G and K.
+
+    ``x0``: X0_ZERO (x = 0) or X0_LINEAR (the linear profile along the flow
+    axis); ``precond``: JACOBI (M = diag d) or NONE (M = I)."""
     keep, a = _args(*_net_args(net))
     P = np.zeros(net.shape, dtype=np.float64) if want_pressure else None
     M = np.zeros(net.shape, dtype=np.uint8) if want_mask else None
     res = _Result()
-    st = _load().rno_solve(*a, float(tol), int(max_iter), _dptr(P),
+    st = _load().rno_solve(*a, float(tol), int(max_iter), int(x0), int(precond), _dptr(P),
                            M.ctypes.data_as(C.POINTER(C.c_uint8)) if M is not None else C.POINTER(C.c_uint8)(),
                            C.byref(res))
     if st and st != -3 and raise_on_error:

@@ -362,8 +362,11 @@ static double cross_section(const lat_t *L)
 
 /* ---------------------------------------------------------------- the solve */
 /*
- * Jacobi-preconditioned CG on the live set, x_0 = 0:
- *   r = b, z = D^-1 r, p = z, rho = r.z
+ * Preconditioned CG on the live set. The preconditioner M is diag(d) (Jacobi,
+ * precond = 0) or the identity (precond = 1); the initial guess x_0 is the
+ * linear profile 1 - c_axis / (n_axis - 1) on live nodes (x0 = 0, the exact
+ * solution of a uniform network) or 0 (x0 = 1):
+ *   r = b - A x_0, z = M^-1 r, p = z, rho = r.z
  *   repeat: q = A p; alpha = rho / p.q; x += alpha p; r -= alpha q;
  *           if ||r|| <= tol ||b||: recompute r = b - A x; stop if still below,
  *             otherwise continue from it with beta = 0, or stop (not
@@ -375,12 +378,14 @@ static double cross_section(const lat_t *L)
  */
 int rno_solve(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodic,
               const double *g0, const double *g1, const double *g2,
-              double tol, int64_t max_iter, double *p_out, uint8_t *mask_out, rno_result *res)
+              double tol, int64_t max_iter, int x0, int precond,
+              double *p_out, uint8_t *mask_out, rno_result *res)
 {
     lat_t L;
     int st = setup(&L, dim, nx, ny, nz, axis, periodic, g0, g1, g2);
     if (st) return st;
     if (!(tol > 0.0) || max_iter < 0 || !res) return RNO_EINVAL;
+    if ((x0 != 0 && x0 != 1) || (precond != 0 && precond != 1)) return RNO_EINVAL;
     memset(res, 0, sizeof(*res));
     size_t N = (size_t)L.N;
     uint8_t *mask = (uint8_t *)malloc(N);
@@ -407,12 +412,23 @@ int rno_solve(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodi
         converged = 1;
         rnorm = 0.0;
     } else {
-        memcpy(r, b, N * sizeof(double));
-        for (size_t i = 0; i < N; ++i) { z[i] = mask[i] == 3 ? r[i] / d[i] : 0.0; p[i] = z[i]; }
+        if (x0 == 0) {
+            const double span = (double)(L.n[L.axis] - 1);
+            for (int64_t i = 0; i < L.N; ++i)
+                x[i] = mask[i] == 3 ? 1.0 - (double)coord(&L, i, L.axis) / span : 0.0;
+        }
+        apply_A(&L, mask, d, x, q);
+        for (size_t i = 0; i < N; ++i) r[i] = b[i] - q[i];
+        for (size_t i = 0; i < N; ++i) {
+            z[i] = mask[i] == 3 ? (precond == 0 ? r[i] / d[i] : r[i]) : 0.0;
+            p[i] = z[i];
+        }
+        rnorm = sqrt(pdot(r, r, L.N));
         double rho = pdot(r, z, L.N);
         double last_check = INFINITY; /* true residual at the previous failed check */
         int restart = 0;
-        while (it < max_iter) {
+        if (rnorm <= tol * bnorm) converged = 1;   /* the initial guess already solves it */
+        while (!converged && it < max_iter) {
             apply_A(&L, mask, d, p, q);
             double pq = pdot(p, q, L.N);
             if (!(pq > 0.0) || !isfinite(pq)) { st = RNO_ENUMERIC; break; }
@@ -432,7 +448,7 @@ int rno_solve(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int periodi
                 last_check = rnorm;
                 restart = 1;
             }
-            for (size_t i = 0; i < N; ++i) z[i] = mask[i] == 3 ? r[i] / d[i] : 0.0;
+            for (size_t i = 0; i < N; ++i) z[i] = mask[i] == 3 ? (precond == 0 ? r[i] / d[i] : r[i]) : 0.0;
             double rho_new = pdot(r, z, L.N);
             double beta = restart ? 0.0 : rho_new / rho;
             restart = 0;

@@ -38,7 +38,10 @@ static int run_case(int dim, int64_t nx, int64_t ny, int64_t nz, int axis, int p
     if (rno_mask_uf(dim, nx, ny, nz, axis, periodic, g[0], g[1], g[2], m2, &l2) != RNO_OK) bad = 1;
     if (!bad && (l1 != l2 || memcmp(m1, m2, (size_t)n) != 0)) bad = 2;
     rno_result res;
-    const int st = rno_solve(dim, nx, ny, nz, axis, periodic, g[0], g[1], g[2], 1e-10, 100000, P, m1, &res);
+    /* x0 = 0 with Jacobi, then the linear initial guess without a preconditioner */
+    int st = rno_solve(dim, nx, ny, nz, axis, periodic, g[0], g[1], g[2], 1e-10, 100000, 1, 0, P, m1, &res);
+    if (st != RNO_OK && st != RNO_ENOCONV) bad = 3;
+    st = rno_solve(dim, nx, ny, nz, axis, periodic, g[0], g[1], g[2], 1e-10, 100000, 0, 1, P, m1, &res);
     if (st != RNO_OK && st != RNO_ENOCONV) bad = 3;
     double out[10];
     if (rno_check_pressure(dim, nx, ny, nz, axis, periodic, g[0], g[1], g[2], P, out) != RNO_OK) bad = 4;
