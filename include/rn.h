@@ -14,8 +14,8 @@
  * other than the flow axis (unit viscosity, bond length and pressure drop).
  *
  * Only interior nodes connected through occupied interior bonds to both
- * faces carry flow (the "live" set). The solve is Jacobi-preconditioned
- * conjugate gradients (Sec. II/IV) on the live set, either all in FP64 or
+ * faces carry flow (the "live" set). The solve is preconditioned conjugate
+ * gradients (Sec. II/IV; Jacobi by default) on the live set, either all in FP64 or
  * with FP32 inner iterations and FP64 residual refreshes, FP64 solution
  * accumulation and FP64 flux (the mixed-precision scheme of Sec. IV).
  *
@@ -67,6 +67,15 @@ extern "C" {
                        and the solve then ends with RN_ENOCONV; scale such inputs, since
                        K is linear in g. */
 
+/* rn_opts.precond */
+#define RN_JACOBI 0  /* M = diag(d), d_i = sum of the node's bond conductances (default) */
+#define RN_NONE 1    /* no preconditioner (M = I) */
+
+/* rn_opts.x0: initial guess of the pressures on the live set */
+#define RN_X0_LINEAR 0  /* 1 - c_axis / (n_axis - 1), the exact solution of a uniform network
+                           with no-flow sides (default) */
+#define RN_X0_ZERO 1    /* 0 */
+
 /* rn_problem.mem */
 #define RN_MEM_HOST 0
 #define RN_MEM_DEVICE 1
@@ -93,15 +102,21 @@ typedef struct {
     int32_t flags;      /* 0 (no-flow sides) or RN_PERIODIC; other bits: RN_EINVAL */
 } rn_problem;
 
-/* Solver options; rn_opts_default() fills the defaults. */
+/* Solver options; rn_opts_default() fills the defaults (all-zero fields other
+ * than tol and max_iter are the defaults too). */
 typedef struct {
     int32_t precision;  /* RN_FP64 (default) or RN_MIXED */
-    int32_t reserved;   /* must be 0 */
+    int32_t precond;    /* RN_JACOBI (default) or RN_NONE */
     double tol;         /* stop when ||b - A x||_2 <= tol ||b||_2, the FP64 true residual on
                            the live set (default 1e-8) */
     int64_t max_iter;   /* cap on CG iterations, i.e. operator applications (default 10^7) */
-    double delta;       /* RN_MIXED: refresh the FP64 residual once the FP32 residual has
-                           fallen by this factor since the last refresh (0 = default 0.1) */
+    double delta;       /* RN_MIXED: the inner tolerance of the FP32 iterations. The FP64
+                           residual is recomputed once the FP32 residual has fallen by this
+                           factor since the last recomputation (0 = default 0.1); the inner
+                           recurrence then continues from the FP64 residual (reliable update).
+                           Ignored by RN_FP64. Must lie in [0, 1). */
+    int32_t x0;         /* RN_X0_LINEAR (default) or RN_X0_ZERO */
+    int32_t reserved;   /* must be 0 */
 } rn_opts;
 
 /* Outcome of one solve. */
@@ -115,7 +130,7 @@ typedef struct {
     double rel_resid;   /* final ||b - A x|| / ||b|| in FP64 (0 when nothing is live) */
     int64_t iters;      /* CG iterations */
     int64_t refreshes;  /* FP64 true-residual refreshes (the first computes b, the second the
-                           residual of the initial guess, the linear profile along the axis) */
+                           residual of the initial guess, rn_opts.x0) */
     int64_t n_live;     /* interior nodes connected to both faces */
     int64_t passes;     /* pass rounds launched while this network iterated (a round launches
                            one pass kernel per kind of network present; idle rounds after
@@ -184,9 +199,10 @@ size_t rn_footprint(const rn_problem *prob, const rn_opts *opts);
 int rn_build_mask(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
 
 /*
- * Solve one network (Sec. II, Eqs. 3-4): mask, Jacobi-PCG from x = 0 on the
- * live set to opts->tol, then fluxes, energy conductance and K, all reduced
- * in FP64 on the device. Writes *out, and prob->p_out / prob->mask_out when
+ * Solve one network (Sec. II, Eqs. 3-4): mask, preconditioned CG (opts->precond,
+ * Jacobi by default) on the live set from the initial guess opts->x0 (the
+ * linear profile along the flow axis by default, or 0) to opts->tol, then
+ * fluxes, energy conductance and K, all reduced in FP64 on the device. Writes *out, and prob->p_out / prob->mask_out when
  * non-NULL. A network with no live node returns RN_OK, converged = 1,
  * iters = 0 and G = K = 0 except for direct inlet-outlet bonds (n_axis = 2).
  * Returns out->status (RN_OK, RN_ENOCONV, RN_ENUMERIC) once the solve ran;

@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "librn.so")
 
 RN_OK, RN_EINVAL, RN_ENOMEM, RN_ENOCONV, RN_ENUMERIC, RN_EDEVICE, RN_EAGAIN, RN_ENOTFOUND = 0, -1, -2, -3, -4, -5, -6, -7
 RN_FP64, RN_MIXED = 0, 1
+RN_JACOBI, RN_NONE = 0, 1
+RN_X0_LINEAR, RN_X0_ZERO = 0, 1
 RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
 RN_PERIODIC = 1
 
@@ -35,8 +37,8 @@ class rn_problem(C.Structure):
 
 
 class rn_opts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("reserved", C.c_int32), ("tol", C.c_double),
-                ("max_iter", C.c_int64), ("delta", C.c_double)]
+    _fields_ = [("precision", C.c_int32), ("precond", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int64), ("delta", C.c_double), ("x0", C.c_int32), ("reserved", C.c_int32)]
 
 
 class rn_result(C.Structure):
@@ -113,10 +115,12 @@ def strerror(code: int) -> str:
         return str(code)
 
 
-def opts(precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000, delta: float = 0.0) -> rn_opts:
+def opts(precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000, delta: float = 0.0,
+         precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR) -> rn_opts:
     o = rn_opts()
     lib().rn_opts_default(C.byref(o))
     o.precision, o.tol, o.max_iter, o.delta = int(precision), float(tol), int(max_iter), float(delta)
+    o.precond, o.x0 = int(precond), int(x0)
     return o
 
 
@@ -126,9 +130,37 @@ def _is_torch(a) -> bool:
 
 @dataclass
 class Problem:
-    """An rn_problem plus references that keep its buffers alive."""
+    """An rn_problem plus references that keep its buffers alive.
+
+    ``device`` is the CUDA device index of its buffers (None: host memory)."""
     c: rn_problem
     keep: list
+    device: Optional[int] = None
+
+
+def _check_device_buffer(name: str, a, n: int, dtype: str, device: Optional[int]) -> int:
+    """Raise ValueError unless `a` is a contiguous CUDA tensor of n elements of
+    `dtype` on `device`; returns its device index."""
+    if not _is_torch(a):
+        raise ValueError(f"{name}: device problems take CUDA tensors for every buffer")
+    if not a.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if str(a.dtype) != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, not {a.dtype}")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if a.numel() != n:
+        raise ValueError(f"{name} has {a.numel()} elements; the lattice has {n} nodes")
+    if device is not None and a.device.index != device:
+        raise ValueError(f"{name} is on cuda:{a.device.index}, the other buffers on cuda:{device}")
+    return a.device.index
+
+
+def _check_host_buffer(name: str, a, n: int, dtype) -> None:
+    if not (isinstance(a, np.ndarray) and a.dtype == dtype and a.flags["C_CONTIGUOUS"]):
+        raise ValueError(f"{name} must be a C-contiguous {np.dtype(dtype).name} numpy array")
+    if a.size != n:
+        raise ValueError(f"{name} has {a.size} elements; the lattice has {n} nodes")
 
 
 def problem(net=None, *, dim=None, nx=None, ny=None, nz=1, axis=0, g: Optional[Sequence] = None,
@@ -148,19 +180,22 @@ def problem(net=None, *, dim=None, nx=None, ny=None, nz=1, axis=0, g: Optional[S
     pr = rn_problem()
     pr.dim, pr.axis, pr.nx, pr.ny, pr.nz = int(dim), int(axis), int(nx), int(ny), int(nz)
     pr.flags = RN_PERIODIC if periodic else 0
+    n = int(nx) * int(ny) * int(nz)
     device = any(_is_torch(a) for a in g if a is not None)
     pr.mem = RN_MEM_DEVICE if device else RN_MEM_HOST
+    dev_index: Optional[int] = None
     for k in range(3):
         a = g[k] if k < len(g) else None
         if a is None:
             pr.g[k] = None
             continue
         if device:
-            if not (a.is_cuda and str(a.dtype) == "torch.float64" and a.is_contiguous()):
-                raise ValueError("device conductances must be contiguous float64 CUDA tensors")
+            dev_index = _check_device_buffer(f"g[{k}]", a, n, "torch.float64", dev_index)
             pr.g[k] = a.data_ptr()
         else:
             a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.size != n:
+                raise ValueError(f"g[{k}] has {a.size} elements; the lattice has {n} nodes")
             pr.g[k] = a.ctypes.data
         keep.append(a)
     for name, arr, dt in (("p_out", p_out, np.float64), ("mask_out", mask_out, np.uint8)):
@@ -168,13 +203,13 @@ def problem(net=None, *, dim=None, nx=None, ny=None, nz=1, axis=0, g: Optional[S
             setattr(pr, name, None)
             continue
         if device:
+            _check_device_buffer(name, arr, n, "torch.float64" if dt is np.float64 else "torch.uint8", dev_index)
             setattr(pr, name, arr.data_ptr())
         else:
-            if not (isinstance(arr, np.ndarray) and arr.dtype == dt and arr.flags["C_CONTIGUOUS"]):
-                raise ValueError(f"{name} must be a C-contiguous {dt.__name__} numpy array")
+            _check_host_buffer(name, arr, n, dt)
             setattr(pr, name, arr.ctypes.data)
         keep.append(arr)
-    return Problem(pr, keep)
+    return Problem(pr, keep, dev_index)
 
 
 class Context:
@@ -186,6 +221,13 @@ class Context:
         if st:
             raise RNError(st)
         self.h = h
+        self.device = int(device)
+
+    def _own(self, prob: "Problem") -> "Problem":
+        """Raise ValueError when a device problem's buffers are on another GPU."""
+        if prob.device is not None and prob.device != self.device:
+            raise ValueError(f"problem buffers are on cuda:{prob.device}, the context on cuda:{self.device}")
+        return prob
 
     def close(self):
         if getattr(self, "h", None):
@@ -221,10 +263,13 @@ class Context:
         lattice direction (x, y, z) or None."""
         dev = _is_torch(noise)
         ptr = (lambda a: a.data_ptr()) if dev else (lambda a: a.ctypes.data)
-        if not dev:
-            for a in (noise, out):
-                if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
-                    raise ValueError("host arrays must be C-contiguous float64")
+        n = int(nx) * int(ny) * int(nz)
+        for name, a in (("noise", noise), ("out", out)):
+            if dev:
+                if _check_device_buffer(name, a, n, "torch.float64", None) != self.device:
+                    raise ValueError(f"{name} is not on the context's device cuda:{self.device}")
+            else:
+                _check_host_buffer(name, a, n, np.float64)
         b = (C.c_double * 3)(*([float(v) for v in beta] + [1.0] * (3 - len(beta)))) if beta is not None else None
         st = lib().rn_fbm_field(self.h, int(dim), int(nx), int(ny), int(nz), float(H), b, C.c_void_p(ptr(noise)),
                                 C.c_void_p(ptr(out)), RN_MEM_DEVICE if dev else RN_MEM_HOST)
@@ -236,11 +281,16 @@ class Context:
         """rn_fbm_bonds: `g_out` (and `u` when given) hold dim arrays like `field`."""
         dev = _is_torch(field)
         ptr = (lambda a: a.data_ptr()) if dev else (lambda a: a.ctypes.data)
+        n = int(nx) * int(ny) * int(nz)
+        if len(g_out) != int(dim) or (u is not None and len(u) != int(dim)):
+            raise ValueError("g_out (and u) need one array per lattice direction")
         arrs = [field] + list(g_out) + (list(u) if u is not None else [])
-        if not dev:
-            for a in arrs:
-                if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]):
-                    raise ValueError("host arrays must be C-contiguous float64")
+        for k, a in enumerate(arrs):
+            if dev:
+                if _check_device_buffer(f"array {k}", a, n, "torch.float64", None) != self.device:
+                    raise ValueError(f"array {k} is not on the context's device cuda:{self.device}")
+            else:
+                _check_host_buffer(f"array {k}", a, n, np.float64)
         DA3 = C.c_void_p * 3
         g3 = DA3(*([ptr(a) for a in g_out] + [None] * (3 - len(g_out))))
         u3 = DA3(*([ptr(a) for a in u] + [None] * (3 - len(u)))) if u is not None else None
@@ -252,14 +302,14 @@ class Context:
 
     def build_mask(self, prob: Problem) -> int:
         nl = C.c_int64(0)
-        st = lib().rn_build_mask(self.h, C.byref(prob.c), C.byref(nl))
+        st = lib().rn_build_mask(self.h, C.byref(self._own(prob).c), C.byref(nl))
         if st:
             raise RNError(st, self.last_error())
         return int(nl.value)
 
     def solve(self, prob: Problem, o: Optional[rn_opts] = None, check: bool = True) -> rn_result:
         res = rn_result()
-        st = lib().rn_solve(self.h, C.byref(prob.c), C.byref(o) if o is not None else None, C.byref(res))
+        st = lib().rn_solve(self.h, C.byref(self._own(prob).c), C.byref(o) if o is not None else None, C.byref(res))
         if check and st not in (RN_OK, RN_ENOCONV):
             raise RNError(st, self.last_error())
         return res
@@ -268,7 +318,7 @@ class Context:
     def solve_batch(self, probs: Sequence[Problem], o=None, check: bool = True) -> List[rn_result]:
         """rn_solve_batch: o is None (defaults), one rn_opts, or a list with one per problem."""
         n = len(probs)
-        arr = (rn_problem * n)(*[pb.c for pb in probs])
+        arr = (rn_problem * n)(*[self._own(pb).c for pb in probs])
         res = (rn_result * n)()
         if o is None:
             opt_arr, n_opts = None, 0
@@ -284,7 +334,7 @@ class Context:
     def submit(self, prob: Problem, o: Optional[rn_opts] = None) -> int:
         """rn_submit: queue a solve; prob's buffers must outlive the ticket."""
         t = C.c_uint64(0)
-        st = lib().rn_submit(self.h, C.byref(prob.c), C.byref(o) if o is not None else None, C.byref(t))
+        st = lib().rn_submit(self.h, C.byref(self._own(prob).c), C.byref(o) if o is not None else None, C.byref(t))
         if st:
             raise RNError(st, self.last_error())
         return int(t.value)
@@ -329,10 +379,11 @@ def rn_solve(ctx: Context, prob: Problem, o: Optional[rn_opts] = None) -> rn_res
 
 
 def solve_network(ctx: Context, net, precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000,
-                  want_pressure: bool = False, want_mask: bool = False, delta: float = 0.0):
+                  want_pressure: bool = False, want_mask: bool = False, delta: float = 0.0,
+                  precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR):
     """Host-memory convenience: returns (rn_result, pressure or None, mask or None)."""
     P = np.zeros(net.shape, dtype=np.float64) if want_pressure else None
     M = np.zeros(net.shape, dtype=np.uint8) if want_mask else None
     pr = problem(net, p_out=P, mask_out=M)
-    res = ctx.solve(pr, opts(precision, tol, max_iter, delta))
+    res = ctx.solve(pr, opts(precision, tol, max_iter, delta, precond, x0))
     return res, P, M

@@ -87,6 +87,14 @@ int tick(rn_ctx *ctx, Sched *S, bool *progressed)
                 *progressed = true;
                 continue;
             }
+            if (S->preparing.empty() && S->finishing.empty() && ctx->engine.active_count() == 0 &&
+                ctx->engine.outstanding() == 0) {
+                // nothing runs that could return memory: waiting would never end
+                S->waiting.pop_front();
+                fail_net(net, RN_ENOMEM);
+                *progressed = true;
+                continue;
+            }
             break;                               // wait until a running network frees memory
         }
         S->waiting.pop_front();
@@ -325,7 +333,7 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
 
 extern "C" {
 
-int rn_version(void) { return 101; }
+int rn_version(void) { return 102; }
 
 const char *rn_strerror(int status)
 {
@@ -338,9 +346,11 @@ int rn_opts_default(rn_opts *o)
     if (!o) return RN_EINVAL;
     std::memset(o, 0, sizeof(*o));
     o->precision = RN_FP64;
+    o->precond = RN_JACOBI;
     o->tol = 1e-8;
     o->max_iter = 10000000;
     o->delta = 0.0;
+    o->x0 = RN_X0_LINEAR;
     return RN_OK;
 }
 
@@ -483,7 +493,7 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
     if (hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (!copy_g && launch_validate(lat, gd, cnt + 1, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (launch_mask(lat, gd, (int *)(base + off_lab), (unsigned *)(base + off_lab + 4 * n),
-                    (uint8_t *)(base + off_mask), (double *)(base + off_P), cnt, ctx->stream) != hipSuccess)
+                    (uint8_t *)(base + off_mask), (double *)(base + off_P), cnt, true, ctx->stream) != hipSuccess)
         return done(RN_EDEVICE);
     if (hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return done(RN_EDEVICE);

@@ -81,6 +81,7 @@ struct PassArgs {
     int ntx, nty, ntz;           // tile counts
     int wrap;                    // bit k: direction k wraps around (periodic sides)
     int tile_z;                  // planes per 3D tile
+    int jacobi;                  // 1: M = diag(d) (z = D^-1 r, u = D^-1 q); 0: M = I (z = r, u = q)
     int ntiles;                  // total workgroup tiles
     int tpw;                     // tiles per workgroup, `grid` tiles apart (2D; 3D: 1)
     int grid;                    // workgroups of this network per pass (multiple of 8 and of groups)
@@ -114,8 +115,10 @@ struct Lat {
 
 // launchers (rn_kernels.hip)
 hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long long *bad, hipStream_t st);
+// linear: the live nodes' initial pressure is the linear profile along the
+// flow axis (else 0)
 hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
-                       double *P, unsigned long long *n_live, hipStream_t st);
+                       double *P, unsigned long long *n_live, bool linear, hipStream_t st);
 template <typename T>
 hipError_t launch_scale(const Lat &L, const double *const g[3], const uint8_t *mask, T *const gT[3], T *vec,
                         int64_t nvec, hipStream_t st);

@@ -64,6 +64,8 @@ int check_opts(const rn_opts *o)
     if (!(o->tol > 0.0) || !std::isfinite(o->tol)) return RN_EINVAL;
     if (o->max_iter < 0) return RN_EINVAL;
     if (!(o->delta >= 0.0) || o->delta >= 1.0) return RN_EINVAL;
+    if (o->precond != RN_JACOBI && o->precond != RN_NONE) return RN_EINVAL;
+    if (o->x0 != RN_X0_LINEAR && o->x0 != RN_X0_ZERO) return RN_EINVAL;
     if (o->reserved != 0) return RN_EINVAL;
     return RN_OK;
 }
@@ -234,6 +236,11 @@ void *Pool::alloc(size_t bytes, hipError_t *err)
         }
     }
     const size_t gib = (size_t)1 << 30;
+    // a new slab: 1 GiB or the request, whichever is larger, within the budget.
+    // When the budget is taken by slabs, the ones nothing is carved from are
+    // released first: otherwise a request larger than every free range would
+    // wait for memory that no running network will ever return.
+    if (reserved_ + bytes > budget_) trim();
     size_t size = std::max(bytes, gib);
     if (reserved_ + size > budget_) size = bytes;
     if (reserved_ + size > budget_) return nullptr;
@@ -251,6 +258,22 @@ void *Pool::alloc(size_t bytes, hipError_t *err)
     reserved_ += size;
     in_use_ += bytes;
     return p;
+}
+
+void Pool::trim()
+{
+    // every pool user frees its range only after the work that uses it has
+    // completed on the stream, so an empty slab has no work in flight
+    std::vector<Slab> keep;
+    for (auto &s : slabs_) {
+        if (s.used_.empty()) {
+            (void)hipFree(s.base);
+            reserved_ -= s.size;
+        } else {
+            keep.push_back(std::move(s));
+        }
+    }
+    slabs_.swap(keep);
 }
 
 void Pool::free(void *ptr)
@@ -361,7 +384,7 @@ int Engine::prepare(Net *net, hipStream_t st, std::string *err)
     int *parent = (int *)(base + L.off_vec);
     unsigned *flags = (unsigned *)(base + L.off_vec + 4 * n);
     ENG_TRY(launch_mask(lat, net->gd, parent, flags, (uint8_t *)(base + L.off_mask), (double *)(base + L.off_P),
-                        cnt, st));
+                        cnt, net->opts.x0 == RN_X0_LINEAR, st));
     if (net->na == 2) ENG_TRY(launch_direct_flux(lat, net->gd[p->axis], (double *)(cnt + 2), st));
     ENG_TRY(hipEventRecord(net->ev_b, st));
     ENG_TRY(hipMemcpyAsync(h_cnt_ + 4 * net->slot, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
@@ -392,6 +415,7 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.ntz = L.ntz;
         A.wrap = wrap_bits(p);
         A.tile_z = L.tile_z;
+        A.jacobi = net->opts.precond == RN_JACOBI ? 1 : 0;
         A.ntiles = L.ntiles;
         A.tpw = L.tpw;
         A.grid = L.grid;

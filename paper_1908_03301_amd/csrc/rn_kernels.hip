@@ -92,6 +92,11 @@ __device__ __forceinline__ T diag_sum(T gxm, T gxp, T gym, T gyp, T gzm, T gzp)
 __device__ __forceinline__ float jscale(float v, float d) { return v * __builtin_amdgcn_rcpf(d); }
 __device__ __forceinline__ double jscale(double v, double d) { return v / d; }
 
+// M^-1 v at a node of diagonal d: v / d with the Jacobi preconditioner, v
+// without one (then every use of d as the weight of M also becomes 1).
+template <typename T>
+__device__ __forceinline__ T apply_minv(T v, T d, bool jacobi) { return jacobi ? jscale(v, d) : v; }
+
 // Scalar update after a CG pass. t = (p.q, z.q, q.D^-1 q, r.z, 0).
 __device__ void step_after_cg(Scalars *s, const double *t)
 {
@@ -423,7 +428,7 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     if constexpr (DIM == 2) dT = diag_sum(gb[0], gb[1], gb[2], gb[3]);
     else dT = diag_sum(gb[0], gb[1], gb[2], gb[3], gb[4], gb[5]);
     const T rs = (T)(r64 / sigma_next);
-    const T zs = dT > T(0) ? jscale(rs, dT) : T(0);
+    const T zs = dT > T(0) ? apply_minv(rs, dT, a.jacobi != 0) : T(0);
     Pd[i] = bonly ? Pi : pi;
     a.dst.z[i] = zs;
     k_.p0[i] = pi_;
@@ -504,6 +509,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ gx = a.gT[0];
     const T *__restrict__ gy = a.gT[1];
     const bool flush = k.flush;        // uniform: this pass adds the pending steps to P
+    const bool jacobi = a.jacobi != 0;
 
     // ---- the FP64 field (every other pass). It does not depend on the
     // stencil: with FP32 vectors it is updated first, which frees its
@@ -658,7 +664,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             const bool face = xaxis ? (x == 0 || x == nx - 1) : (yy == 0 || yy == ny - 1);
             const bool live = ok && d > T(0) && !face;
             if (!live) qv = T(0);
-            const T uv = live ? jscale(qv, d) : T(0);
+            const T uv = live ? apply_minv(qv, d, jacobi) : T(0);
             // every in-lattice node is stored (zeros and unchanged pressures off the
             // live set) so that cache lines are written whole
             if (ok) {
@@ -674,7 +680,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             acc[0] += dp * dq;
             acc[1] += dz * dq;
             acc[2] += dq * du;
-            acc[3] += (double)d * dz * dz;
+            acc[3] += (double)(jacobi ? d : T(1)) * dz * dz;
         }
     }
 }
@@ -798,6 +804,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ gy = a.gT[1];
     const T *__restrict__ gz = a.gT[2];
     const bool flush = k.flush;        // uniform: this pass adds the pending steps to P
+    const bool jacobi = a.jacobi != 0;
     const double sa = k.sa, sa2 = k.sa2;
     const int yw = y0 + w * kRows;                 // first row of this wave
     bool rok[kRows], lok[kRows];                   // lattice node / slot holding a node or an image
@@ -950,7 +957,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
                                       : (ax == 1 ? (yy == 0 || yy == ny - 1) : (zc == 0 || zc == nz - 1));
             const bool live = rok[j] && d > T(0) && !face;
             if (!live) qv = T(0);
-            const T uv = live ? jscale(qv, d) : T(0);
+            const T uv = live ? apply_minv(qv, d, jacobi) : T(0);
             if (rok[j]) {
                 const int64_t i = rowoff[j] + (int64_t)zc * sz;
                 pd[i] = p0;
@@ -961,7 +968,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             acc[0] += dp * dq;
             acc[1] += dz * dq;
             acc[2] += dq * du;
-            acc[3] += (double)d * dz * dz;
+            acc[3] += (double)(jacobi ? d : T(1)) * dz * dz;
         }
         // rotate
 #pragma unroll
@@ -1147,10 +1154,10 @@ __global__ void uf_flags_kernel(Lat L, const double *ga, int *parent, unsigned *
 }
 
 // Mask byte, initial pressure field (faces 1 / 0, dead nodes 1 when tied to
-// the inlet only, live nodes the linear profile 1 - c_axis / (n_axis - 1),
-// the CG's initial guess) and the live count.
+// the inlet only, live nodes the CG's initial guess: the linear profile
+// 1 - c_axis / (n_axis - 1) when `linear`, else 0) and the live count.
 __global__ void mask_final_kernel(Lat L, int *parent, const unsigned *flags, uint8_t *mask, double *P,
-                                  unsigned long long *n_live)
+                                  unsigned long long *n_live, int linear)
 {
     unsigned long long cnt = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.n;
@@ -1169,10 +1176,10 @@ __global__ void mask_final_kernel(Lat L, int *parent, const unsigned *flags, uin
         } else {
             m = (uint8_t)flags[uf_find(parent, (int)i)];
             p0 = (m == 1) ? 1.0 : 0.0;
-            if (m == 3) {   // initial guess on the live set: the linear profile along the flow axis
+            if (m == 3) {   // initial guess on the live set: the linear profile along the flow axis, or 0
                 const int ca = L.axis == 0 ? x : (L.axis == 1 ? y : z);
                 const int na = L.axis == 0 ? L.nx : (L.axis == 1 ? L.ny : L.nz);
-                p0 = 1.0 - (double)ca / (double)(na - 1);
+                p0 = linear ? 1.0 - (double)ca / (double)(na - 1) : 0.0;
                 ++cnt;
             }
         }
@@ -1256,14 +1263,14 @@ hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long
 }
 
 hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
-                       double *P, unsigned long long *n_live, hipStream_t st)
+                       double *P, unsigned long long *n_live, bool linear, hipStream_t st)
 {
     const int gr = grid_for(L.n);
     const double *g2 = L.dim == 3 ? g[2] : nullptr;
     uf_init_kernel<<<gr, kBlock, 0, st>>>(L.n, parent, flags);
     uf_union_kernel<<<gr, kBlock, 0, st>>>(L, g[0], g[1], g2, parent);
     uf_flags_kernel<<<gr, kBlock, 0, st>>>(L, g[L.axis], parent, flags);
-    mask_final_kernel<<<gr, kBlock, 0, st>>>(L, parent, flags, mask, P, n_live);
+    mask_final_kernel<<<gr, kBlock, 0, st>>>(L, parent, flags, mask, P, n_live, linear ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -21,8 +21,9 @@
 namespace rn {
 
 // ------------------------------------------------------------------ memory pool
-// Device memory in slabs (hipMalloc'd on demand, released with the context),
-// carved first-fit. The sum of slab sizes never exceeds the context budget.
+// Device memory in slabs (hipMalloc'd on demand, released with the context or
+// when a request needs their budget), carved first-fit. The sum of slab sizes
+// never exceeds the context budget.
 class Pool {
 public:
     explicit Pool(size_t budget = 0) : budget_(budget) {}
@@ -34,6 +35,9 @@ public:
     void *alloc(size_t bytes, hipError_t *err);
     void free(void *p);
     void release_all();
+    // hipFree every slab that nothing is carved from
+    void trim();
+    size_t reserved() const { return reserved_; }
 
 private:
     struct Slab {

@@ -58,6 +58,58 @@ def test_struct_layout_matches_header(lib):
     assert [int(v) for v in out] == [C.sizeof(B.rn_problem), C.sizeof(B.rn_opts), C.sizeof(B.rn_result)]
 
 
+def test_opts_field_offsets_match_header(lib):
+    fields = [f for f, _ in B.rn_opts._fields_]
+    src = '#include "rn.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(){' + "".join(
+        f'printf("%zu ", offsetof(rn_opts, {f}));' for f in fields) + 'return 0;}\n'
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        open(os.path.join(d, "t.c"), "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), os.path.join(d, "t.c"), "-o",
+                               os.path.join(d, "t")])
+        out = subprocess.check_output([os.path.join(d, "t")]).decode().split()
+    assert [int(v) for v in out] == [getattr(B.rn_opts, f).offset for f in fields]
+
+
+def test_opts_precond_and_initial_guess(lib):
+    o = B.rn_opts()
+    assert lib.rn_opts_default(C.byref(o)) == B.RN_OK
+    assert o.precond == B.RN_JACOBI and o.x0 == B.RN_X0_LINEAR and o.reserved == 0
+    p = _prob()
+    for prec in (B.RN_JACOBI, B.RN_NONE):
+        for x0 in (B.RN_X0_LINEAR, B.RN_X0_ZERO):
+            assert B.rn_validate(p, B.opts(precond=prec, x0=x0)) == B.RN_OK
+    for field, bad in (("precond", 2), ("precond", -1), ("x0", 2), ("x0", -1), ("reserved", 1)):
+        o = B.opts()
+        setattr(o, field, bad)
+        assert B.rn_validate(p, o) == B.RN_EINVAL, field
+        assert B.rn_footprint(p, o) > 0                # the footprint does not depend on them
+
+
+def test_binding_rejects_mismatched_buffers(lib):
+    """The binding checks every buffer's element count, dtype, layout and
+    memory space before a pointer reaches the library."""
+    import torch
+    net = I.uniform_network(2, 8, 6)
+    with pytest.raises(ValueError, match="elements"):
+        B.problem(dim=2, nx=8, ny=6, nz=1, g=[net.g[0], net.g[1][:5]])
+    with pytest.raises(ValueError, match="elements"):
+        B.problem(net, p_out=np.zeros((6, 7)))
+    with pytest.raises(ValueError, match="float64"):
+        B.problem(net, p_out=np.zeros((6, 8), dtype=np.float32))
+    with pytest.raises(ValueError, match="uint8"):
+        B.problem(net, mask_out=np.zeros((6, 8), dtype=np.int8))
+    with pytest.raises(ValueError, match="contiguous"):
+        B.problem(net, p_out=np.zeros((8, 6)).T)
+    # device problems take CUDA tensors only (here: CPU tensors are rejected)
+    gt = [torch.from_numpy(a) for a in net.g]
+    with pytest.raises(ValueError, match="CUDA"):
+        B.problem(dim=2, nx=8, ny=6, nz=1, g=gt)
+    ok = B.problem(net, p_out=np.zeros((6, 8)), mask_out=np.zeros((6, 8), dtype=np.uint8))
+    assert ok.device is None and ok.c.mem == B.RN_MEM_HOST
+
+
 def _prob(**kw):
     net = I.uniform_network(2, 8, 6)
     p = B.problem(net)
