@@ -197,3 +197,47 @@ def dual_2d_fast(net: Network) -> Network:
     gyd[-1, :] = 0.0
     gyd[0: nx - 2, 1:ny] = 1.0 / gy[: ny - 1, 1: nx - 1].T
     return Network(2, ny + 1, nx - 1, 1, [gxd, gyd], 0, {"kind": "dual"})
+
+
+def energy(net: Network, P: np.ndarray) -> float:
+    """Dissipation sum over occupied bonds of g (P_i - P_j)^2 of a full pressure field.
+
+    For a field that holds the face values (1 / 0) and the oracle's convention
+    off the live set, this is the energy form of the conductance: its minimum
+    over the live-set pressures is G, reached at the solution x*, and for any
+    other live-set field x it exceeds G by exactly (x - x*)^T A (x - x*)
+    (the Dirichlet principle). Every term is >= 0, so the sum has no
+    cancellation (numpy sums pairwise).
+    """
+    I, J, Gv = bond_list(net)
+    Pf = np.asarray(P, dtype=np.float64).ravel()
+    occ = Gv > 0
+    d = Pf[I[occ]] - Pf[J[occ]]
+    return float(np.sum(Gv[occ] * d * d))
+
+
+def face_path_resistance(net: Network) -> np.ndarray:
+    """Per node, the least series resistance sum(1/g) of a path of occupied
+    bonds to any node of either face (inf where there is none; 0 on faces).
+
+    For a live node i this bounds (A^-1)_ii, the effective resistance between
+    i and the two faces held at the same potential: by Rayleigh's monotonicity
+    law, removing every bond but one path can only raise it.
+    """
+    from scipy.sparse.csgraph import dijkstra
+    I, J, Gv = bond_list(net)
+    occ = Gv > 0
+    W = sp.coo_matrix((1.0 / Gv[occ], (I[occ], J[occ])), shape=(net.n, net.n)).tocsr()
+    src = np.nonzero(faces(net) != 0)[0]
+    return dijkstra(W, directed=False, indices=src, min_only=True).reshape(net.shape)
+
+
+def pressure_error_bound(R: np.ndarray, E_field: float, G_star: float, rel_round: float = 1e-14) -> np.ndarray:
+    """Bound on |x_i - x*_i| at live nodes from the energy excess of a field.
+
+    x_i - x*_i = (A^-1 e_i)^T A (x - x*) <= sqrt((A^-1)_ii) ||x - x*||_A, with
+    ||x - x*||_A^2 = E(x) - G* and (A^-1)_ii <= R_i (face_path_resistance).
+    rel_round allows for the rounding of the two energy sums.
+    """
+    excess = max(E_field - G_star, 0.0) + rel_round * abs(G_star)
+    return np.sqrt(R * excess)
