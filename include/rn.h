@@ -250,6 +250,30 @@ int rn_submit(rn_ctx *ctx, const rn_problem *prob, const rn_opts *opts, uint64_t
  */
 int rn_poll(rn_ctx *ctx, uint64_t ticket, rn_result *out);
 
+/* rn_plan_t.path: which pass kernel runs a network */
+#define RN_PATH_2D_FULL 0   /* 2D, full tiles (64 x segments columns, 4 waves of rows) */
+#define RN_PATH_2D_SMALL 1  /* 2D, quarter-size tiles (one 64-column segment, half the rows) */
+#define RN_PATH_3D 2        /* 3D, 64 x 16 x tile_z blocks streamed along z */
+
+/* Launch plan of one network: the tile its pass kernel uses and how many
+ * workgroups one pass of it takes. The plan depends only on the network's
+ * shape, dimension and precision, so a network runs the same arithmetic alone,
+ * in a batch or in the served stream. */
+typedef struct {
+    int32_t path;          /* RN_PATH_* */
+    int32_t tiles_per_wg;  /* tiles one workgroup runs per pass (2D: 1 or 2; 3D: 1) */
+    int32_t tile_x, tile_y, tile_z;   /* nodes per tile along x, y, z (tile_z = 1 in 2D) */
+    int32_t tiles;         /* tiles covering the lattice */
+    int32_t workgroups;    /* workgroups per pass (a multiple of 8) */
+    int32_t groups;        /* completion-counter groups of the cross-workgroup reduction */
+    int64_t footprint;     /* device bytes of the solve (rn_footprint) */
+} rn_plan_t;
+
+/* Fill *out with the launch plan of `prob` under `opts` (NULL: defaults)
+ * without touching a device. RN_EINVAL for an invalid shape or options (the
+ * conductances themselves are not read). */
+int rn_plan(const rn_problem *prob, const rn_opts *opts, rn_plan_t *out);
+
 /* Scheduler occupancy of a context (for monitoring and admission tests). */
 typedef struct {
     int64_t waiting;      /* queued, waiting for memory or a control slot */

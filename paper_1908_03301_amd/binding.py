@@ -23,10 +23,11 @@ RN_JACOBI, RN_NONE = 0, 1
 RN_X0_LINEAR, RN_X0_ZERO = 0, 1
 RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
 RN_PERIODIC = 1
+RN_PATH_2D_FULL, RN_PATH_2D_SMALL, RN_PATH_3D = 0, 1, 2
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
-            "rn_submit", "rn_poll", "rn_stats", "rn_fbm_field", "rn_fbm_bonds"]
+            "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"]
 
 
 class rn_problem(C.Structure):
@@ -55,6 +56,15 @@ class rn_result(C.Structure):
 class rn_stats_t(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("waiting", "preparing", "active", "finishing", "bytes_in_use", "budget",
                                           "launches", "peak_active")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rn_plan_t(C.Structure):
+    _fields_ = [("path", C.c_int32), ("tiles_per_wg", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+                ("tile_z", C.c_int32), ("tiles", C.c_int32), ("workgroups", C.c_int32), ("groups", C.c_int32),
+                ("footprint", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -96,13 +106,14 @@ def lib():
         L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
         L.rn_poll.argtypes = [C.c_void_p, C.c_uint64, P(rn_result)]
         L.rn_stats.argtypes = [C.c_void_p, P(rn_stats_t)]
+        L.rn_plan.argtypes = [P(rn_problem), P(rn_opts), P(rn_plan_t)]
         D, DA3 = P(C.c_double), C.c_void_p * 3
         L.rn_fbm_field.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_double, D, C.c_void_p, C.c_void_p,
                                    C.c_int32]
         L.rn_fbm_bonds.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_void_p, C.c_double, C.c_int32,
                                    P(DA3), C.c_double, P(DA3), C.c_int32]
         for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve",
-                  "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_fbm_field", "rn_fbm_bonds"):
+                  "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -360,6 +371,15 @@ def rn_validate(prob: Problem, o: Optional[rn_opts] = None) -> int:
 
 def rn_footprint(prob: Problem, o: Optional[rn_opts] = None) -> int:
     return int(lib().rn_footprint(C.byref(prob.c), C.byref(o) if o is not None else None))
+
+
+def rn_plan(prob: Problem, o: Optional[rn_opts] = None) -> dict:
+    """rn_plan: the launch plan of a network as a dict (RNError if invalid)."""
+    out = rn_plan_t()
+    st = lib().rn_plan(C.byref(prob.c), C.byref(o) if o is not None else None, C.byref(out))
+    if st:
+        raise RNError(st)
+    return out.as_dict()
 
 
 def rn_version() -> int:

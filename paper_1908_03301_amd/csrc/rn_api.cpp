@@ -451,6 +451,37 @@ size_t rn_footprint(const rn_problem *p, const rn_opts *o)
     return make_layout(p, o ? o : &d).total;
 }
 
+int rn_plan(const rn_problem *p, const rn_opts *opts, rn_plan_t *out)
+{
+    if (!out) return RN_EINVAL;
+    int st = check_shape(p);
+    if (st) return st;
+    rn_opts o;
+    if (opts) o = *opts;
+    else rn_opts_default(&o);
+    if ((st = check_opts(&o))) return st;
+    const Layout L = make_layout(p, &o);
+    std::memset(out, 0, sizeof(*out));
+    if (p->dim == 3) {
+        out->path = RN_PATH_3D;
+        out->tile_x = kTX;
+        out->tile_y = kTY;
+        out->tile_z = L.tile_z;
+    } else {
+        const bool f32 = L.s == 4;
+        out->path = L.shape ? RN_PATH_2D_SMALL : RN_PATH_2D_FULL;
+        out->tile_x = L.shape ? kWave : kWave * (f32 ? kSEG2f : kSEG2d);
+        out->tile_y = (kBlock / kWave) * (L.shape ? (f32 ? kTY2fS : kTY2dS) : (f32 ? kTY2f : kTY2d));
+        out->tile_z = 1;
+    }
+    out->tiles_per_wg = L.tpw;
+    out->tiles = L.ntiles;
+    out->workgroups = L.grid;
+    out->groups = L.groups;
+    out->footprint = (int64_t)L.total;
+    return RN_OK;
+}
+
 int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
 {
     if (!ctx) return RN_EINVAL;

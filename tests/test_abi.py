@@ -58,6 +58,36 @@ def test_struct_layout_matches_header(lib):
     assert [int(v) for v in out] == [C.sizeof(B.rn_problem), C.sizeof(B.rn_opts), C.sizeof(B.rn_result)]
 
 
+def test_plan_struct_and_paths(lib):
+    """rn_plan: layout of rn_plan_t as the host compiler sees rn.h, and the
+    path each lattice takes (no device call)."""
+    src = '#include "rn.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%zu %zu %zu",' \
+          'sizeof(rn_plan_t),offsetof(rn_plan_t,groups),offsetof(rn_plan_t,footprint));return 0;}\n'
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        open(os.path.join(d, "t.c"), "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), os.path.join(d, "t.c"), "-o",
+                               os.path.join(d, "t")])
+        out = [int(v) for v in subprocess.check_output([os.path.join(d, "t")]).decode().split()]
+    assert out == [C.sizeof(B.rn_plan_t), B.rn_plan_t.groups.offset, B.rn_plan_t.footprint.offset]
+    small = B.problem(dim=2, nx=128, ny=128, g=[np.ones(128 * 128)] * 2)
+    p = B.rn_plan(small, B.opts(B.RN_MIXED))
+    assert p["path"] == B.RN_PATH_2D_SMALL and p["tile_z"] == 1 and p["tiles"] >= 1
+    assert p["workgroups"] % 8 == 0 and p["footprint"] == B.rn_footprint(small, B.opts(B.RN_MIXED))
+    n = 1024 * 1024
+    full = B.problem(dim=2, nx=1024, ny=1024, g=[np.ones(n), np.ones(n)])
+    p = B.rn_plan(full, B.opts(B.RN_FP64))
+    assert p["path"] == B.RN_PATH_2D_FULL and p["tiles"] * p["tile_x"] * p["tile_y"] >= n
+    n3 = 64 ** 3
+    cube = B.problem(dim=3, nx=64, ny=64, nz=64, g=[np.ones(n3)] * 3)
+    p = B.rn_plan(cube, B.opts(B.RN_MIXED))
+    assert p["path"] == B.RN_PATH_3D and p["tile_x"] == 64 and p["tile_z"] >= 2
+    bad = B.rn_problem()
+    assert lib.rn_plan(C.byref(bad), None, C.byref(B.rn_plan_t())) == B.RN_EINVAL
+    assert lib.rn_plan(C.byref(small.c), None, None) == B.RN_EINVAL
+
+
 def test_opts_field_offsets_match_header(lib):
     fields = [f for f, _ in B.rn_opts._fields_]
     src = '#include "rn.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(){' + "".join(
