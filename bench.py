@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the random-network flow solve on one MI355X.
 
-One step solves one synthetic network for K_x and K_y (two solves) with the
-mixed-precision solver (FP32 inner CG, FP64 residual refresh, solution and
-flux) to a relative true residual of 1e-8; plain FP64 CG is timed on the same
-inputs and tolerance for comparison. Inputs are generated on the host, copied
-to HBM before the timed region and passed by device pointer.
+Default workload: the 512-network batch (2D sides 64-1024 and 3D sides
+32-128, FBM conductances, diluted), solved together by rn_solve_batch with
+the mixed-precision solver (FP32 inner CG, FP64 residual refresh, solution
+and flux) to a relative true residual of 1e-8. One step = one batch. Inputs
+are generated on the host, copied to HBM before the timed region and passed
+by device pointer.
 
-Prints one JSON line: value = network solves/s (mixed), latency percentiles,
-the pass kernel's roofline (algorithmic bytes / device time of the iteration
-loop, measured with HIP events on the launch stream) and the CPU oracle timed
-on a bounded sample of the same workload.
+Prints one JSON line: value = network solves/s, the members' completion
+latencies, the dominant pass kernel's roofline (floor bytes per swept node
+over its device time, from HIP events the library records on the launch
+stream around every launch), the plain FP64 CG comparisons (batched, one at a
+time, and a Poisson-served stream against FIFO), and the CPU oracle's full
+solves of a seeded sample of the members. The single-network workloads
+(--workload fbm2d_2048, iid2d_128, strat3d_256) and the study workloads
+(serve, aniso, fbmgen) remain available.
 """
 from __future__ import annotations
 
@@ -86,17 +91,19 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str, precision: str):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if current."""
+def traffic_from_profiles(workload: str, key: str):
+    """Counted HBM bytes per launch of one kernel on one workload, from the
+    committed rocprofv3 counter summaries, if they were taken on the current
+    kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "pass_kernel_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        e = d.get(workload, {}).get(precision)
+        e = d.get(workload, {}).get(key)
         if not e or e.get("kernel_hash") != kernel_hash():
             return None
-        return float(e["bytes_per_launch"])
+        return {"bytes_per_launch": float(e["bytes_per_launch"])}
     except Exception:
         return None
 
@@ -147,9 +154,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="fbm2d_2048", choices=sorted(WORKLOADS) + sorted(MULTI))
-    ap.add_argument("--requests", type=int, default=96, help="serve: number of requests")
-    ap.add_argument("--pool", type=int, default=24, help="serve: distinct networks generated for the stream")
+    ap.add_argument("--workload", default="batch512", choices=sorted(WORKLOADS) + sorted(MULTI))
+    ap.add_argument("--requests", type=int, default=160,
+                    help="served stream: requests after the saturation run (batch512: 0 skips the leg)")
+    ap.add_argument("--sat-requests", type=int, default=48,
+                    help="served stream: requests submitted at once to measure the saturation rate")
+    ap.add_argument("--pool", type=int, default=32, help="served stream: distinct networks generated for it")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="batch512: members the CPU oracle solves")
     ap.add_argument("--batch-size", type=int, default=512, help="batch512: networks in the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
@@ -228,7 +239,8 @@ def main():
     live_iters = sum(r["n_live"] * r["iters"] for _, r in res_m)
     avg_launch_s = loop_t / max(launches, 1)
     achieved = alg_bytes / loop_t / 1e9
-    traffic = traffic_from_profiles(args.workload, "mixed")
+    tr = traffic_from_profiles(args.workload, "mixed")
+    traffic = tr["bytes_per_launch"] if tr else None
     copy_gbps = copy_ceiling_gbps()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
@@ -331,11 +343,78 @@ def _net_bytes(r, dim, n, s):
     return r.iters * pb["cg"] + r.refreshes * pb["refresh"]
 
 
+# Algorithmic bytes per swept node (every lattice node of the network): the
+# compulsory floor of one CG iteration, s (d + 7) (bonds read once; x, r, p
+# read and written once; the Jacobi diagonal read once), and of one FP64
+# outer step of the mixed solve, 8 d + 32 (FP64 bonds and residual, the
+# solution read and written). The two-pass fused design figure s (d + 12) is
+# reported beside it.
+def floor_cg(dim: int, s: int) -> int:
+    return s * (dim + 7)
+
+
+def floor_refresh(dim: int) -> int:
+    return 8 * dim + 32
+
+
+def two_pass_cg(dim: int, s: int) -> int:
+    return s * (dim + 12)
+
+
+PATHS = ("2d_full", "2d_small", "3d")
+KERNEL_NAME = {(0, "fp32"): "pass2d_kernel<float, 0>", (1, "fp32"): "pass2d_kernel<float, 1>",
+               (2, "fp32"): "pass3d_kernel<float>", (0, "fp64"): "pass2d_kernel<double, 0>",
+               (1, "fp64"): "pass2d_kernel<double, 1>", (2, "fp64"): "pass3d_kernel<double>"}
+
+
+def kernel_accounting(B, nets, probs, results_per_step, precision, stats):
+    """Per pass kernel (path x precision): device time and launches from the
+    library's event timing, algorithmic bytes from every member's iteration and
+    refresh counts (floor figures per swept node), and the live-node bytes of
+    the pass as built (pass_bytes) beside them."""
+    s = 4 if precision == B.RN_MIXED else 8
+    pname = "fp32" if precision == B.RN_MIXED else "fp64"
+    plan_path = [B.rn_plan(pr, B.opts(precision))["path"] for pr in probs]
+    rows = {}
+    for path in range(3):
+        secs = stats["pass_device_s"][path][precision]
+        launches = stats["pass_timed_launches"][path][precision]
+        if launches == 0:
+            continue
+        floor_b = live_b = two_b = 0
+        cg = refr = swept_iters = 0
+        for res in results_per_step:
+            for k, (net, r) in enumerate(zip(nets, res)):
+                if plan_path[k] != path:
+                    continue
+                floor_b += r.iters * floor_cg(net.dim, s) * net.n + r.refreshes * floor_refresh(net.dim) * net.n
+                two_b += r.iters * two_pass_cg(net.dim, s) * net.n + r.refreshes * floor_refresh(net.dim) * net.n
+                pb = pass_bytes(net.dim, net.n, s, r.n_live)
+                live_b += r.iters * pb["cg"] + r.refreshes * pb["refresh"]
+                cg += r.iters
+                refr += r.refreshes
+                swept_iters += r.iters * net.n
+        rows[f"{PATHS[path]}_{pname}"] = {
+            "kernel": KERNEL_NAME[(path, pname)], "device_s": secs, "launches": launches,
+            "avg_launch_us": 1e6 * secs / launches, "cg_passes": cg, "refresh_passes": refr,
+            "floor_bytes": floor_b, "two_pass_bytes": two_b, "live_node_bytes": live_b,
+            "floor_GBps": floor_b / secs / 1e9, "swept_node_iters_per_s": swept_iters / secs}
+    return rows
+
+
 def batch_bench(args, B, I, np):
     """512 uneven networks solved together (rn_solve_batch), mixed precision to tol.
 
-    Compared with the same batch in FP64, and with plain FP64 CG run one
-    network at a time (rn_solve per network, in order).
+    value = networks solved per second over the timed batches. Latency is the
+    completion time of each member from the call. The roofline is the pass
+    kernel with the most device time (HIP events around every launch, on the
+    launch stream, over the timed batches): the floor bytes of every CG
+    iteration and FP64 outer step of its members over its device time.
+    Compared with the same batch in FP64, with plain FP64 CG run one network
+    at a time, and with a Poisson-served stream against plain FP64 CG served
+    first in first out (--requests 0 skips it). The CPU oracle solves a seeded
+    sample of the members in worker processes while the GPU comparison legs
+    run.
     """
     import torch
     specs = I.batch_specs(args.batch_size)
@@ -345,52 +424,157 @@ def batch_bench(args, B, I, np):
     probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=0, g=g) for n, g in zip(nets, gd)]
     ctx = B.Context(0)
 
-    def run(prec, steps):
-        walls, res = [], None
+    def run(prec, steps, timed_stats=False):
+        walls, per_step, lat = [], [], []
         for it in range(args.warmup + steps):
+            if timed_stats and it == args.warmup:
+                ctx.set_timing(True)           # clears the accumulated launch times
             torch.cuda.synchronize()
             t = time.perf_counter()
             res = ctx.solve_batch(probs, B.opts(prec, args.tol))
             w = time.perf_counter() - t
             bad = [r.status for r in res if r.status != 0]
-            print(f"[bench] batch prec={prec} {'warmup' if it < args.warmup else 'step'} {it}: {w:.3f}s "
-                  f"failed={len(bad)}", file=sys.stderr, flush=True)
+            print(f"[bench] batch prec={'mixed' if prec == B.RN_MIXED else 'fp64'} "
+                  f"{'warmup' if it < args.warmup else 'step'} {it}: {w:.3f}s failed={len(bad)}",
+                  file=sys.stderr, flush=True)
             if bad:
                 raise SystemExit(f"batch members failed: {bad[:5]}")
             if it >= args.warmup:
                 walls.append(w)
-        return walls, res
+                per_step.append(res)
+                lat.extend(r.t_total_s for r in res)
+        st = ctx.stats() if timed_stats else None
+        if timed_stats:
+            ctx.set_timing(False)
+        return walls, per_step, lat, st
 
-    walls_m, res_m = run(B.RN_MIXED, args.steps)
+    walls_m, steps_m, lat_m, st_m = run(B.RN_MIXED, args.steps, timed_stats=True)
     tot_m = sum(walls_m)
     value = len(probs) * len(walls_m) / tot_m
-    bytes_m = sum(_net_bytes(r, n.dim, n.n, 4) for r, n in zip(res_m, nets))
-    out = _contract(args, value, "solves/s", tot_m, len(walls_m),
-                    {"workload": MULTI["batch512"], "networks": len(probs), "nodes": sum(n.n for n in nets),
-                     "tol": args.tol, "precision": "fp32 inner CG + fp64 refresh/solution/flux",
-                     "inputs": "resident in HBM"})
-    out["batch_wall_s"] = round(min(walls_m), 3)
-    out["roofline"] = {"bound": "hbm", "achieved": round(bytes_m / min(walls_m) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": round(bytes_m / min(walls_m) / 1e9 / HBM_PEAK_GBS, 4),
-                       "traffic": None, "kernel": "pass2d/pass3d_kernel<float> (all networks per launch)",
-                       "note": "algorithmic bytes of every member's passes / batch wall time"}
-    if args.no_fp64:
-        ctx.close()
-        return out
-    walls_d, res_d = run(B.RN_FP64, 1)
-    out["fp64_batched_solves_per_s"] = round(len(probs) / min(walls_d), 4)
-    # plain FP64 CG, one network at a time
-    t = time.perf_counter()
-    for pr in probs:
-        r = ctx.solve(pr, B.opts(B.RN_FP64, args.tol))
-        if r.status != 0:
-            raise SystemExit(f"fp64 solve failed: {r.as_dict()}")
-    w = time.perf_counter() - t
-    out["fp64_cg_one_at_a_time_solves_per_s"] = round(len(probs) / w, 4)
-    out["mixed_batched_vs_fp64_one_at_a_time"] = round(value / out["fp64_cg_one_at_a_time_solves_per_s"], 3)
-    out["max_K_rel_diff_mixed_vs_fp64"] = float(max(abs(a.K / b.K - 1.0) for a, b in zip(res_m, res_d) if b.K > 0))
+    res_m = steps_m[-1]
+    config = {"workload": MULTI["batch512"], "networks": len(probs), "nodes": int(sum(n.n for n in nets)),
+              "nodes_2d": int(sum(n.n for n in nets if n.dim == 2)),
+              "nodes_3d": int(sum(n.n for n in nets if n.dim == 3)), "tol": args.tol,
+              "precision": "fp32 inner CG + fp64 refresh/solution/flux", "x0": "linear profile",
+              "preconditioner": "Jacobi", "inputs": "resident in HBM"}
+    out = _contract(args, value, "solves/s", tot_m, len(walls_m), config)
+    out["latency_ms"] = {"p50": round(1e3 * float(np.percentile(lat_m, 50)), 2),
+                         "p99": round(1e3 * float(np.percentile(lat_m, 99)), 2),
+                         "of": "completion time of each batch member from the rn_solve_batch call"}
+    out["batch_wall_s"] = [round(w, 3) for w in walls_m]
+    kern = kernel_accounting(B, nets, probs, steps_m, B.RN_MIXED, st_m)
+    dom_key = max(kern, key=lambda k: kern[k]["device_s"])
+    dom = kern[dom_key]
+    traffic = traffic_from_profiles("batch512", dom_key)
+    achieved = dom["floor_GBps"]
+    out["roofline"] = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": round(traffic["bytes_per_launch"]) if traffic else None,
+        "kernel": dom["kernel"], "avg_launch_us": round(dom["avg_launch_us"], 2), "launches": dom["launches"],
+        "bytes_per_launch": round(dom["floor_bytes"] / dom["launches"]),
+        "bytes_model": "floor per swept node: s(d+7) per CG iteration, 8d+32 per FP64 outer step",
+        "two_pass_GBps": round(dom["two_pass_bytes"] / dom["device_s"] / 1e9, 1),
+        "live_node_GBps": round(dom["live_node_bytes"] / dom["device_s"] / 1e9, 1),
+        "traffic_GBps": round(traffic["bytes_per_launch"] / (dom["device_s"] / dom["launches"]) / 1e9, 1)
+        if traffic else None,
+        "timing": "HIP events recorded by the library on the launch stream between consecutive pass launches"}
+    out["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                      for k, v in kern.items()}
+    all_secs = sum(v["device_s"] for v in kern.values())
+    all_floor = sum(v["floor_bytes"] for v in kern.values())
+    out["all_pass_kernels_floor_GBps"] = round(all_floor / all_secs / 1e9, 1)
+    out["pass_device_s_per_batch"] = round(all_secs / len(walls_m), 4)
+    out["live_node_iters_per_s"] = round(sum(r.n_live * r.iters for res in steps_m for r in res) / tot_m, 1)
+    out["iters_mixed"] = {"median": int(np.median([r.iters for r in res_m])),
+                          "max": int(max(r.iters for r in res_m))}
+
+    cpu_job = None
+    if not args.no_cpu:
+        cpu_job = start_cpu_baseline(specs, args)
+
+    if not args.no_fp64:
+        walls_d, steps_d, _, _ = run(B.RN_FP64, 1)
+        res_d = steps_d[-1]
+        out["fp64_batched_solves_per_s"] = round(len(probs) / min(walls_d), 4)
+        # plain FP64 CG, one network at a time
+        t = time.perf_counter()
+        lat_d = []
+        for pr in probs:
+            r = ctx.solve(pr, B.opts(B.RN_FP64, args.tol))
+            if r.status != 0:
+                raise SystemExit(f"fp64 solve failed: {r.as_dict()}")
+            lat_d.append(time.perf_counter() - t)
+        w = time.perf_counter() - t
+        out["fp64_cg_one_at_a_time"] = {"solves_per_s": round(len(probs) / w, 4),
+                                        "p50_ms": round(1e3 * float(np.percentile(lat_d, 50)), 2),
+                                        "p99_ms": round(1e3 * float(np.percentile(lat_d, 99)), 2)}
+        out["mixed_batched_vs_fp64_one_at_a_time"] = round(value / out["fp64_cg_one_at_a_time"]["solves_per_s"], 3)
+        out["mixed_batched_vs_fp64_batched"] = round(value / out["fp64_batched_solves_per_s"], 3)
+        out["max_K_rel_diff_mixed_vs_fp64"] = float(max(abs(a.K / b.K - 1.0) for a, b in zip(res_m, res_d)
+                                                        if b.K > 0))
     ctx.close()
+    del gd, probs
+    torch.cuda.empty_cache()
+
+    if args.requests > 0:
+        out["serve"] = serve_leg(args, B, I, np)
+
+    if cpu_job is not None:
+        out["cpu_baseline"] = finish_cpu_baseline(cpu_job, args)
+        out["vs_cpu_oracle"] = round(value / out["cpu_baseline"]["value"], 1)
     return out
+
+
+def _oracle_member(job):
+    """One full oracle solve (mask, assembly, Jacobi-PCG from the linear
+    profile, flux) of batch member k in this worker process; seconds and
+    iterations."""
+    k, spec, tol = job
+    import oracle
+    from paper_1908_03301_amd import inputs as I
+    net = I.batch_network(spec)
+    t = time.perf_counter()
+    r = oracle.solve(net, tol=tol, want_pressure=False, x0=oracle.X0_LINEAR, precond=oracle.JACOBI)
+    return k, time.perf_counter() - t, r.iters, r.converged, net.n
+
+
+def start_cpu_baseline(specs, args):
+    """Start the oracle on a seeded uniform sample of the batch members, one
+    member per worker process (single-threaded C), on the host's cores while
+    the GPU comparison legs run."""
+    from concurrent.futures import ProcessPoolExecutor
+    import numpy as np
+    rng = np.random.default_rng(190803301 + 77)
+    sample = sorted(int(k) for k in rng.choice(len(specs), size=min(args.cpu_sample, len(specs)), replace=False))
+    # the box's CPU share is 16 cores; two stay free for the threads driving the GPU
+    cores = max(1, min(16, len(os.sched_getaffinity(0))) - 2)
+    ex = ProcessPoolExecutor(max_workers=cores)
+    futs = [ex.submit(_oracle_member, (k, specs[k], args.tol)) for k in sample]
+    print(f"[bench] cpu oracle: {len(sample)} sampled members on {cores} worker processes", file=sys.stderr,
+          flush=True)
+    return {"ex": ex, "futs": futs, "cores": cores, "sample": sample, "t0": time.perf_counter(),
+            "members": len(specs)}
+
+
+def finish_cpu_baseline(job, args):
+    rows = [f.result() for f in job["futs"]]
+    wall = time.perf_counter() - job["t0"]
+    job["ex"].shutdown()
+    secs = sum(r[1] for r in rows)
+    cores = job["cores"]
+    one = len(rows) / secs
+    return {"value": round(one * cores, 4), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "value_1_core": round(one, 5),
+            "sample": (f"{len(rows)} of the {job['members']} batch members (seeded uniform draw: "
+                       f"{job['sample']}), each solved in full by the oracle (mask, assembly, Jacobi-PCG from "
+                       f"the linear profile to tol {args.tol}, flux) in its own single-threaded worker process; "
+                       f"value = cores x sampled solves / their summed solve seconds ({secs:.1f} s; wall "
+                       f"{wall:.1f} s on {cores} processes), i.e. the batch's solves/s on that many cores "
+                       f"under a uniform sample"),
+            "members": [{"member": r[0], "nodes": r[4], "seconds": round(r[1], 2), "iters": r[2],
+                         "converged": bool(r[3])} for r in rows],
+            "cpu": cpu_info(), "threads_per_solve": 1}
 
 
 def aniso_bench(args, B, I, np):
@@ -477,14 +661,15 @@ def fbmgen_bench(args, B, I, np):
     return out
 
 
-def serve_bench(args, B, I, np):
-    """Served stream (rn_submit / rn_poll) vs plain FP64 CG served first-in first-out.
+def serve_leg(args, B, I, np):
+    """Served stream (rn_submit / rn_poll) against plain FP64 CG served first in first out.
 
-    Requests cycle through a pool of pre-generated networks (device resident).
-    The mixed server's saturation rate is measured first with all requests
-    submitted at once; the stream then arrives as a Poisson process at 0.7
-    times that rate. The same arrival times are replayed against plain FP64
-    CG solving one request at a time in arrival order.
+    Requests cycle through a pool of pre-generated networks (device
+    resident). The mixed server's saturation rate is measured first with
+    --sat-requests requests submitted at once; the stream then arrives as a
+    Poisson process at 0.7 times that rate. The same arrival times are
+    replayed against plain FP64 CG solving one request at a time in arrival
+    order. Latency = completion time - arrival time.
     """
     import torch
     reqs = I.stream_requests(args.pool, rate_per_s=1.0)
@@ -493,10 +678,9 @@ def serve_bench(args, B, I, np):
     torch.cuda.synchronize()
     probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=0, g=g) for n, g in zip(pool, gd)]
     om, od = B.opts(B.RN_MIXED, args.tol), B.opts(B.RN_FP64, args.tol)
-    nreq = args.requests
-    order = [i % len(pool) for i in range(nreq)]
 
-    def serve(arrivals, c):
+    def serve(arrivals, order, c):
+        nreq = len(arrivals)
         lat, submitted, done = [None] * nreq, {}, 0
         tstart = time.perf_counter()
         i = 0
@@ -518,19 +702,24 @@ def serve_bench(args, B, I, np):
         return lat, time.perf_counter() - tstart
 
     # saturation: everything submitted at t = 0
+    nsat = args.sat_requests
     c = B.Context(0)
-    _, make = serve([0.0] * nreq, c)
-    sat = nreq / make
+    _, make = serve([0.0] * nsat, [i % len(pool) for i in range(nsat)], c)
+    sat = nsat / make
     c.close()
     rate = 0.7 * sat
+    nreq = args.requests
     rng = I.rng_for(50_000_000)
     arrivals = list(np.cumsum(rng.exponential(1.0 / rate, nreq)))
+    order = [int(k) for k in rng.integers(0, len(pool), nreq)]
+    print(f"[bench] serve: saturation {sat:.2f} solves/s, stream of {nreq} at {rate:.2f}/s", file=sys.stderr,
+          flush=True)
     c = B.Context(0)
-    lat, make = serve(arrivals, c)
+    lat, make = serve(arrivals, order, c)
     c.close()
     # plain FP64 CG, first in first out, same arrivals
     ctx = B.Context(0)
-    lat_d, tfree = [], 0.0
+    lat_d = []
     tstart = time.perf_counter()
     for k in range(nreq):
         now = time.perf_counter() - tstart
@@ -542,34 +731,49 @@ def serve_bench(args, B, I, np):
         lat_d.append(time.perf_counter() - tstart - arrivals[k])
     make_d = time.perf_counter() - tstart
     ctx.close()
-    value = nreq / make
-    out = _contract(args, value, "solves/s", make, nreq,
-                    {"workload": MULTI["serve"], "requests": nreq, "pool": len(pool), "rate_per_s": round(rate, 3),
-                     "saturation_solves_per_s": round(sat, 3), "tol": args.tol,
+    del gd, probs
+    torch.cuda.empty_cache()
+    out = {"workload": MULTI["serve"], "requests": nreq, "pool": len(pool),
+           "pool_nodes": int(sum(n.n for n in pool)), "rate_per_s": round(rate, 3),
+           "saturation_solves_per_s": round(sat, 3), "saturation_requests": nsat,
+           "solves_per_s": round(nreq / make, 3),
+           "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+           "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+           "fp64_cg_fifo": {"solves_per_s": round(nreq / make_d, 3),
+                            "p50_ms": round(1e3 * float(np.percentile(lat_d, 50)), 2),
+                            "p99_ms": round(1e3 * float(np.percentile(lat_d, 99)), 2)}}
+    out["p99_vs_fp64_fifo"] = round(out["fp64_cg_fifo"]["p99_ms"] / out["p99_ms"], 3)
+    return out
+
+
+def serve_bench(args, B, I, np):
+    """The served stream alone (value = its solves/s at 0.7 x saturation)."""
+    leg = serve_leg(args, B, I, np)
+    out = _contract(args, leg["solves_per_s"], "solves/s", leg["requests"] / leg["solves_per_s"], leg["requests"],
+                    {"workload": MULTI["serve"], "requests": leg["requests"], "pool": leg["pool"],
+                     "rate_per_s": leg["rate_per_s"], "tol": args.tol,
                      "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"})
-    out["latency_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 2),
-                         "p99": round(1e3 * float(np.percentile(lat, 99)), 2)}
-    out["fp64_cg_fifo"] = {"solves_per_s": round(nreq / make_d, 3),
-                           "p50_ms": round(1e3 * float(np.percentile(lat_d, 50)), 2),
-                           "p99_ms": round(1e3 * float(np.percentile(lat_d, 99)), 2)}
+    out["latency_ms"] = {"p50": leg["p50_ms"], "p99": leg["p99_ms"]}
+    out["serve"] = leg
     return out
 
 
 def cpu_baseline(net, wl, args, res_fp64):
-    """The CPU oracle (plain C, FP64, one thread) on a bounded sample of the workload.
+    """The CPU oracle (plain C, FP64, one thread) on a bounded sample of a single-network workload.
 
     Sample: mask + assembly + final flux on the full network (max_iter 0), and
-    the same plus `cpu_iters` PCG iterations; the per-solve time is extrapolated
-    to the iteration count the GPU FP64 solve of the same network needed (same
-    Jacobi-PCG from x = 0 and the same tolerance).
+    the same plus `cpu_iters` PCG iterations; the per-solve time is
+    extrapolated to the iteration count the GPU FP64 solve of the same network
+    needed (the same Jacobi-PCG from the same linear-profile initial guess and
+    the same tolerance). The batch workload times full oracle solves instead.
     """
     import oracle
     n0 = net.with_axis(wl["axes"][0])
     t0 = time.perf_counter()
-    oracle.solve(n0, tol=args.tol, max_iter=0, want_pressure=False)
+    oracle.solve(n0, tol=args.tol, max_iter=0, want_pressure=False, x0=oracle.X0_LINEAR)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.solve(n0, tol=args.tol, max_iter=args.cpu_iters, want_pressure=False)
+    oracle.solve(n0, tol=args.tol, max_iter=args.cpu_iters, want_pressure=False, x0=oracle.X0_LINEAR)
     t_m = time.perf_counter() - t0
     t_iter = max(t_m - t_setup, 1e-9) / args.cpu_iters
     if res_fp64:

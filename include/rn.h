@@ -274,6 +274,42 @@ typedef struct {
  * conductances themselves are not read). */
 int rn_plan(const rn_problem *prob, const rn_opts *opts, rn_plan_t *out);
 
+/* ------------------------------------------------------------------ launch shapes
+ * The launch shape of each network's pass kernel (RN_PATH_* tile, tiles per
+ * workgroup, 3D tile depth) comes from a process-wide table indexed by size
+ * class (floor(log2 of the node count)), dimension and inner precision; an
+ * entry the table does not set follows built-in rules (the defaults). The
+ * paper's kernels ran on a fixed 256 x 64 launch grid (Sec. IV); here the
+ * shapes are measured on the device. The table changes only through the
+ * three calls below, so a network's shape, and with it its arithmetic, is the
+ * same alone, in a batch and in the served stream; a network queued or
+ * running keeps the shape it was given when it was submitted.
+ */
+#define RN_TUNE_QUICK 1   /* rn_autotune: only classes up to 2^18 (2D) / 2^17 (3D) nodes */
+
+/*
+ * Measure every candidate shape of every size class (2D: 2^12 .. 2^24 nodes,
+ * full or small tile x 1 or 2 tiles per workgroup; 3D: 2^15 .. 2^24 nodes,
+ * tile depth 2 .. 32 planes) in both precisions on ctx's device: for each, a
+ * few identical synthetic networks of the class are solved together for 48
+ * CG passes and the pass kernels' device time per node and pass is taken from
+ * the event timing of rn_set_timing. The fastest shape of each class is
+ * installed process-wide and, if cache_path is not NULL, written to that file
+ * (text, one line per class; rn_tune_load reads it back). Takes seconds and
+ * device memory from the context's budget. Do not solve on other contexts
+ * while it runs (the trials install their candidates process-wide). flags: 0
+ * or RN_TUNE_QUICK. RN_EINVAL (bad flags, the server is running, the cache
+ * file cannot be written), RN_ENOMEM, RN_EDEVICE.
+ */
+int rn_autotune(rn_ctx *ctx, const char *cache_path, int32_t flags);
+
+/* Install the table written by rn_autotune to `path` (host only). RN_EINVAL
+ * when the file cannot be read or a line is malformed (nothing installed). */
+int rn_tune_load(const char *path);
+
+/* Back to the built-in rules for every class. */
+int rn_tune_reset(void);
+
 /* Scheduler occupancy of a context (for monitoring and admission tests). */
 typedef struct {
     int64_t waiting;      /* queued, waiting for memory or a control slot */
@@ -284,9 +320,26 @@ typedef struct {
     int64_t budget;       /* the context's HBM budget */
     int64_t launches;     /* pass kernel launches issued so far */
     int64_t peak_active;  /* most networks that have shared one pass launch */
+    /* With rn_set_timing on: device time of the pass kernel launches, by the
+     * path that ran them (RN_PATH_*) and their inner precision (RN_FP64,
+     * RN_MIXED), measured with HIP events recorded on the launch stream
+     * between consecutive launches, and the number of launches timed. */
+    double pass_device_s[3][2];
+    int64_t pass_timed_launches[3][2];
 } rn_stats_t;
 
 int rn_stats(rn_ctx *ctx, rn_stats_t *out);
+
+/*
+ * Turn the per-launch timing of rn_stats on (enable = 1) or off (0). While it
+ * is on, one HIP event is recorded on the launch stream after every pass
+ * launch (and one before each chunk of launches); the elapsed time between
+ * consecutive events is added to pass_device_s of the launch's path and
+ * precision when the chunk's control blocks are read back. Turning it on
+ * clears the accumulated times. Off by default; ignored while pass rounds
+ * are replayed from a hipGraph (RN_GRAPHS=1). Thread-safe like rn_stats.
+ */
+int rn_set_timing(rn_ctx *ctx, int enable);
 
 /* ------------------------------------------------------------------ inputs on the GPU
  * Correlated conductance fields (Sec. II, Eqs. 1-2), the input generation the

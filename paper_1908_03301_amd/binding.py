@@ -27,7 +27,9 @@ RN_PATH_2D_FULL, RN_PATH_2D_SMALL, RN_PATH_3D = 0, 1, 2
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
-            "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"]
+            "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds",
+            "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset"]
+RN_TUNE_QUICK = 1
 
 
 class rn_problem(C.Structure):
@@ -55,10 +57,15 @@ class rn_result(C.Structure):
 
 class rn_stats_t(C.Structure):
     _fields_ = [(k, C.c_int64) for k in ("waiting", "preparing", "active", "finishing", "bytes_in_use", "budget",
-                                          "launches", "peak_active")]
+                                          "launches", "peak_active")] + \
+               [("pass_device_s", (C.c_double * 2) * 3), ("pass_timed_launches", (C.c_int64 * 2) * 3)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {}
+        for k, _ in self._fields_:
+            v = getattr(self, k)
+            out[k] = [[v[a][b] for b in range(2)] for a in range(3)] if k.startswith("pass_") else v
+        return out
 
 
 class rn_plan_t(C.Structure):
@@ -106,13 +113,19 @@ def lib():
         L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
         L.rn_poll.argtypes = [C.c_void_p, C.c_uint64, P(rn_result)]
         L.rn_stats.argtypes = [C.c_void_p, P(rn_stats_t)]
+        L.rn_set_timing.argtypes = [C.c_void_p, C.c_int]
+        L.rn_autotune.argtypes = [C.c_void_p, C.c_char_p, C.c_int32]
+        L.rn_tune_load.argtypes = [C.c_char_p]
+        L.rn_tune_reset.argtypes = []
         L.rn_plan.argtypes = [P(rn_problem), P(rn_opts), P(rn_plan_t)]
         D, DA3 = P(C.c_double), C.c_void_p * 3
         L.rn_fbm_field.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_double, D, C.c_void_p, C.c_void_p,
                                    C.c_int32]
         L.rn_fbm_bonds.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_void_p, C.c_double, C.c_int32,
                                    P(DA3), C.c_double, P(DA3), C.c_int32]
-        for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask", "rn_solve",
+        for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask",
+                  "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset",
+                  "rn_solve",
                   "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -356,6 +369,18 @@ class Context:
         st = lib().rn_poll(self.h, C.c_uint64(ticket), C.byref(res))
         return st, res
 
+    def set_timing(self, enable: bool) -> None:
+        """rn_set_timing: per-launch device timing of the pass kernels into stats()."""
+        st = lib().rn_set_timing(self.h, int(bool(enable)))
+        if st:
+            raise RNError(st)
+
+    def autotune(self, cache_path: Optional[str] = None, quick: bool = False) -> None:
+        """rn_autotune: measure the launch shapes on this device and install them process-wide."""
+        st = lib().rn_autotune(self.h, cache_path.encode() if cache_path else None, RN_TUNE_QUICK if quick else 0)
+        if st:
+            raise RNError(st, self.last_error())
+
     def stats(self) -> dict:
         s = rn_stats_t()
         st = lib().rn_stats(self.h, C.byref(s))
@@ -380,6 +405,17 @@ def rn_plan(prob: Problem, o: Optional[rn_opts] = None) -> dict:
     if st:
         raise RNError(st)
     return out.as_dict()
+
+
+def rn_tune_load(path: str) -> None:
+    """rn_tune_load: install a launch-shape table file (host only)."""
+    st = lib().rn_tune_load(path.encode())
+    if st:
+        raise RNError(st)
+
+
+def rn_tune_reset() -> None:
+    lib().rn_tune_reset()
 
 
 def rn_version() -> int:

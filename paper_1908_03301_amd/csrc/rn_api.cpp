@@ -12,7 +12,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 
 using namespace rn;
 
@@ -75,6 +77,9 @@ int tick(rn_ctx *ctx, Sched *S, bool *progressed)
 {
     *progressed = false;
     hipStream_t st = ctx->stream;
+    // on a caller's stream everything stays on it (the caller's work that
+    // produces device inputs is ordered before the setup)
+    ctx->engine.set_side(ctx->stream == ctx->own ? ctx->side : nullptr);
     // 1. admit waiting networks while memory and control slots allow
     while (!S->waiting.empty() && !ctx->engine.full()) {
         Net *net = S->waiting.front();
@@ -317,6 +322,7 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
         if (r) {
             fail_all(ctx, S, r);
             (void)hipStreamSynchronize(ctx->stream);
+            (void)hipStreamSynchronize(ctx->side);
         }
     }
     int first = RN_OK;
@@ -327,6 +333,72 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
         release_net(nets[i]);
     }
     return r ? r : first;
+}
+
+// ------------------------------------------------------------------ launch-shape search
+// A trial runs `copies` identical networks of one size class together (so
+// that a round moves at least ~4 M nodes, as in a batch) for kTrialPasses CG
+// passes from x = 0 (the tolerance is out of reach), with one candidate
+// shape installed for that class, and measures the device time of the pass
+// launches per node and pass with the library's event timing.
+constexpr int kTrialPasses = 48;
+
+int shape_trial(rn_ctx *ctx, int dim, int s, int side, int copies, const ShapeChoice &cand, double *ns_per_node)
+{
+    const int64_t n = dim == 2 ? (int64_t)side * side : (int64_t)side * side * side;
+    ShapeTable t = shape_table_get();
+    t.c[dim - 2][s == 4 ? 1 : 0][shape_class(n)] = cand;
+    shape_table_install(t);
+    std::vector<rn_problem> probs((size_t)copies);
+    hipError_t he;
+    char *gmem = (char *)ctx->pool.alloc((size_t)8 * dim * n * copies, &he);
+    if (!gmem) return he != hipSuccess ? RN_EDEVICE : RN_ENOMEM;
+    int r = RN_OK;
+    for (int c = 0; c < copies && !r; ++c) {
+        rn_problem &p = probs[(size_t)c];
+        std::memset(&p, 0, sizeof(p));
+        p.dim = dim;
+        p.axis = 0;
+        p.nx = p.ny = side;
+        p.nz = dim == 3 ? side : 1;
+        p.mem = RN_MEM_DEVICE;
+        for (int k = 0; k < dim; ++k) {
+            double *g = (double *)gmem + ((size_t)c * dim + k) * (size_t)n;
+            p.g[k] = g;
+            if (launch_fill_trial(g, n, (uint32_t)(977 * c + 131 * k + 7), ctx->stream) != hipSuccess) r = RN_EDEVICE;
+        }
+    }
+    if (!r && hipStreamSynchronize(ctx->stream) != hipSuccess) r = RN_EDEVICE;
+    if (!r) {
+        rn_opts o;
+        rn_opts_default(&o);
+        o.precision = s == 4 ? RN_MIXED : RN_FP64;
+        o.tol = 1e-30;
+        o.max_iter = kTrialPasses;
+        o.x0 = RN_X0_ZERO;
+        std::vector<rn_result> res((size_t)copies);
+        {
+            std::lock_guard<std::mutex> lk(ctx->call_mu);
+            ctx->engine.set_timing(true);
+        }
+        const int st = solve_many(ctx, copies, probs.data(), &o, 1, res.data());
+        double secs = 0.0;
+        {
+            std::lock_guard<std::mutex> lk(ctx->call_mu);
+            for (int k = 0; k < Engine::kKinds; ++k)
+                if ((Engine::kind_path(k) == RN_PATH_3D) == (dim == 3) && Engine::kind_precision(k) == o.precision)
+                    secs += ctx->engine.kind_seconds(k);
+            ctx->engine.set_timing(false);
+        }
+        int64_t passes = 0;
+        for (const rn_result &x : res) passes = std::max(passes, x.passes);
+        if (st != RN_OK && st != RN_ENOCONV) r = st;
+        else if (passes <= 0 || secs <= 0.0) r = RN_EDEVICE;
+        else *ns_per_node = 1e9 * secs / ((double)passes * (double)copies * (double)n);
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->pool.free(gmem);
+    return r;
 }
 
 }  // namespace
@@ -377,6 +449,7 @@ int rn_create(int device, size_t budget, rn_ctx **out)
     ctx->budget = budget ? budget : (size_t)(0.9 * (double)free_b);
     ctx->pool.set_budget(ctx->budget);
     if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) return fail();
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) return fail();
     ctx->stream = ctx->own;
     if (ctx->engine.init(ctx->stream, &ctx->err)) return fail();
     ctx->engine_ok = true;
@@ -399,6 +472,7 @@ int rn_destroy(rn_ctx *ctx)
     }
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     fbm_release(ctx);
     Sched *S = nullptr;
     {
@@ -416,6 +490,7 @@ int rn_destroy(rn_ctx *ctx)
     if (ctx->engine_ok) ctx->engine.destroy();
     ctx->pool.release_all();
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     delete ctx;
     return RN_OK;
 }
@@ -599,6 +674,110 @@ int rn_stats(rn_ctx *ctx, rn_stats_t *out)
     out->budget = (int64_t)ctx->pool.budget();
     out->launches = ctx->engine.launches();
     out->peak_active = ctx->engine.peak_active();
+    for (int k = 0; k < Engine::kKinds; ++k) {
+        const int pa = Engine::kind_path(k), pr = Engine::kind_precision(k);
+        out->pass_device_s[pa][pr] += ctx->engine.kind_seconds(k);
+        out->pass_timed_launches[pa][pr] += ctx->engine.kind_launches(k);
+    }
+    return RN_OK;
+}
+
+int rn_autotune(rn_ctx *ctx, const char *cache_path, int32_t flags)
+{
+    if (!ctx || (flags & ~RN_TUNE_QUICK)) return RN_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(ctx->call_mu);
+        if (ctx->server) return RN_EINVAL;
+        if (hipSetDevice(ctx->device) != hipSuccess) return RN_EDEVICE;
+    }
+    const bool quick = (flags & RN_TUNE_QUICK) != 0;
+    ShapeTable result;   // built-in rules wherever nothing is measured
+    shape_table_install(result);
+    int r = RN_OK;
+    for (int dim = 2; dim <= 3 && !r; ++dim)
+        for (int s : {4, 8}) {
+            if (r) break;
+            const int c_lo = dim == 2 ? 12 : 15, c_hi = quick ? (dim == 2 ? 18 : 17) : 24;
+            for (int cls = c_lo; cls <= c_hi && !r; ++cls) {
+                // a side whose node count falls in the class
+                int side = (int)std::llround(std::pow(2.0, (cls + 0.5) / dim));
+                auto nodes = [&](int sd) { return dim == 2 ? (int64_t)sd * sd : (int64_t)sd * sd * sd; };
+                while (shape_class(nodes(side)) > cls) --side;
+                while (shape_class(nodes(side)) < cls) ++side;
+                const int64_t n = nodes(side);
+                const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 22) / n));
+                std::vector<ShapeChoice> cands;
+                if (dim == 2) {
+                    for (int shape : {0, 1})
+                        for (int tpw : {1, 2}) {
+                            ShapeChoice c;
+                            c.shape = shape;
+                            c.tpw = tpw;
+                            cands.push_back(c);
+                        }
+                } else {
+                    for (int tz : {2, 4, 8, 16, 32})
+                        if (tz <= side) {
+                            ShapeChoice c;
+                            c.tile_z = tz;
+                            cands.push_back(c);
+                        }
+                }
+                ShapeChoice best;
+                double best_ns = 0.0;
+                for (const ShapeChoice &c : cands) {
+                    double ns = 0.0;
+                    r = shape_trial(ctx, dim, s, side, copies, c, &ns);
+                    if (r) break;
+                    if (best_ns == 0.0 || ns < best_ns) {
+                        best = c;
+                        best_ns = ns;
+                    }
+                }
+                if (r) break;
+                best.ns_per_node = best_ns;
+                result.c[dim - 2][s == 4 ? 1 : 0][cls] = best;
+            }
+        }
+    shape_table_install(result);
+    if (r) return r;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "w");
+        if (!f) return RN_EINVAL;
+        const std::string text = shape_table_format(result);
+        const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+        if (std::fclose(f) != 0 || !ok) return RN_EINVAL;
+    }
+    return RN_OK;
+}
+
+int rn_tune_load(const char *path)
+{
+    if (!path) return RN_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return RN_EINVAL;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+    std::fclose(f);
+    ShapeTable t;
+    if (shape_table_parse(text, &t) != RN_OK) return RN_EINVAL;
+    shape_table_install(t);
+    return RN_OK;
+}
+
+int rn_tune_reset(void)
+{
+    shape_table_install(ShapeTable());
+    return RN_OK;
+}
+
+int rn_set_timing(rn_ctx *ctx, int enable)
+{
+    if (!ctx || (enable != 0 && enable != 1)) return RN_EINVAL;
+    CallLock cl(ctx);
+    ctx->engine.set_timing(enable != 0);
     return RN_OK;
 }
 

@@ -86,6 +86,8 @@ struct PassArgs {
     int tpw;                     // tiles per workgroup, `grid` tiles apart (2D; 3D: 1)
     int grid;                    // workgroups of this network per pass (multiple of 8 and of groups)
     int groups;                  // completion-ticket groups (power of two, divides grid)
+    int64_t round0;              // engine pass round of the network's first pass (persistent launches
+                                 // wait for round - round0 completed passes before a round's item)
     // FP64 data
     const double *g64[3];        // original conductances
     double *P[2];                // full FP64 pressure field: CG passes after refresh m add their
@@ -116,13 +118,18 @@ struct Lat {
 // launchers (rn_kernels.hip)
 hipError_t launch_validate(const Lat &L, const double *const g[3], unsigned long long *bad, hipStream_t st);
 // linear: the live nodes' initial pressure is the linear profile along the
-// flow axis (else 0)
+// flow axis (else 0); P may be null (mask and live count only)
 hipError_t launch_mask(const Lat &L, const double *const g[3], int *parent, unsigned *flags, uint8_t *mask,
                        double *P, unsigned long long *n_live, bool linear, hipStream_t st);
 template <typename T>
 hipError_t launch_scale(const Lat &L, const double *const g[3], const uint8_t *mask, T *const gT[3], T *vec,
                         int64_t nvec, hipStream_t st);
 hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
+// zero n <= 64 counters with a kernel (no memset node, so a captured graph may hold it)
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st);
+// g[i] in [1, 2) from a hash of i and salt (the networks of the launch-shape trials)
+hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st);
+
 // One pass of every network in the block table blk[0..nblocks): entry
 // (network, local block); tab[2 * network + parity] are that network's
 // arguments and scal[network] its control block. dim: 2 (2D, full tiles),
@@ -131,6 +138,15 @@ hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipSt
 template <typename T>
 hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks, int parity,
                        int slot, hipStream_t st);
+// `rounds` pass rounds of every network in the block table in one launch
+// (rounds round_base .. round_base + rounds - 1 of the engine); dim, tab,
+// blk, scal, nblocks and slot as for launch_pass. *err (device memory, zero on
+// entry) becomes nonzero when a wait exceeded its bound; *queue (device
+// memory, one 8-byte word the launcher clears) is the launch's item counter.
+template <typename T>
+hipError_t launch_pass_persist(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks,
+                               int64_t round_base, int rounds, int slot, unsigned *err, unsigned long long *queue,
+                               hipStream_t st);
 
 // tile geometry of the pass kernels: a 2D workgroup tile is 64 kSEG2f x
 // 4 kTY2f (FP32) or 64 kSEG2d x 4 kTY2d (FP64): each wave holds kTY2f / kTY2d

@@ -15,7 +15,10 @@
 #include <cstdlib>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <string>
 
 namespace rn {
 
@@ -129,6 +132,100 @@ constexpr int kWGTarget2D = 1024, kTpwMax2D = 2, kSmall2D = 128;
 constexpr int kResident3D = 512;   // 3D workgroups resident at once (256 CUs x 2)
 
 
+// ------------------------------------------------------------------ launch-shape table
+
+namespace {
+std::mutex g_shape_mu;
+ShapeTable g_shapes;   // every entry follows the built-in rules until a table is installed
+}  // namespace
+
+int shape_class(int64_t n)
+{
+    int c = 0;
+    while (c + 1 < kShapeClasses && ((int64_t)1 << (c + 1)) <= n) ++c;
+    return c;
+}
+
+ShapeChoice shape_choice(int dim, int s, int64_t n)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    return g_shapes.c[dim == 3 ? 1 : 0][s == 4 ? 1 : 0][shape_class(n)];
+}
+
+ShapeTable shape_table_get()
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    return g_shapes;
+}
+
+void shape_table_install(const ShapeTable &t)
+{
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    g_shapes = t;
+}
+
+bool shape_choice_valid(int dim, const ShapeChoice &c)
+{
+    if (dim == 2) return c.shape < 0 || ((c.shape == 0 || c.shape == 1) && c.tpw >= 1 && c.tpw <= 4);
+    return c.tile_z == 0 || (c.tile_z >= 1 && c.tile_z <= 64);
+}
+
+// Text form, one line per tuned entry:
+//   <dim> <fp32|fp64> <class> <shape> <tiles per workgroup> <tile_z> <ns per node and pass>
+// ('#' starts a comment line).
+std::string shape_table_format(const ShapeTable &t)
+{
+    std::string out = "# librn launch shapes: dim precision class shape tiles_per_wg tile_z ns_per_node_pass\n";
+    char line[160];
+    for (int d = 0; d < 2; ++d)
+        for (int f = 0; f < 2; ++f)
+            for (int c = 0; c < kShapeClasses; ++c) {
+                const ShapeChoice &e = t.c[d][f][c];
+                if (d == 0 ? e.shape < 0 : e.tile_z == 0) continue;
+                std::snprintf(line, sizeof(line), "%d %s %d %d %d %d %.6f\n", d + 2, f ? "fp32" : "fp64", c, e.shape,
+                              e.tpw, e.tile_z, e.ns_per_node);
+                out += line;
+            }
+    return out;
+}
+
+int shape_table_parse(const std::string &text, ShapeTable *out)
+{
+    ShapeTable t;
+    size_t pos = 0;
+    while (pos < text.size()) {
+        size_t end = text.find('\n', pos);
+        if (end == std::string::npos) end = text.size();
+        std::string line = text.substr(pos, end - pos);
+        pos = end + 1;
+        const size_t first = line.find_first_not_of(" \t\r");
+        if (first == std::string::npos || line[first] == '#') continue;
+        int dim = 0, cls = -1, shape = 0, tpw = 0, tz = 0, used = 0;
+        char prec[8] = {0};
+        double ns = 0.0;
+        if (std::sscanf(line.c_str(), "%d %7s %d %d %d %d %lf %n", &dim, prec, &cls, &shape, &tpw, &tz, &ns, &used) < 7)
+            return RN_EINVAL;
+        if (line.find_first_not_of(" \t\r", (size_t)used) != std::string::npos) return RN_EINVAL;
+        const std::string ps(prec);
+        if ((dim != 2 && dim != 3) || (ps != "fp32" && ps != "fp64") || cls < 0 || cls >= kShapeClasses)
+            return RN_EINVAL;
+        ShapeChoice e;
+        e.ns_per_node = ns;
+        if (dim == 2) {
+            e.shape = shape;
+            e.tpw = tpw;
+            if (shape < 0) return RN_EINVAL;
+        } else {
+            e.tile_z = tz;
+            if (tz <= 0) return RN_EINVAL;
+        }
+        if (!shape_choice_valid(dim, e) || !std::isfinite(ns) || ns < 0.0) return RN_EINVAL;
+        t.c[dim - 2][ps == "fp32" ? 1 : 0][cls] = e;
+    }
+    *out = t;
+    return RN_OK;
+}
+
 Layout make_layout(const rn_problem *p, const rn_opts *o)
 {
     Layout L;
@@ -144,14 +241,16 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
         // 1024^2 the small tile was no faster alone and slower in batches.
         L.ntx = div_up((int)p->nx, kWave * (L.s == 4 ? kSEG2f : kSEG2d));
         L.nty = div_up((int)p->ny, (L.s == 4 ? kTY2f : kTY2d) * (kBlock / kWave));
-        L.shape = L.ntx * L.nty < kSmall2D ? 1 : 0;
+        const ShapeChoice ch = shape_choice(2, L.s, L.n);
+        L.shape = ch.shape >= 0 ? ch.shape : (L.ntx * L.nty < kSmall2D ? 1 : 0);
         if (L.shape) {
             L.ntx = div_up((int)p->nx, kWave);
             L.nty = div_up((int)p->ny, (L.s == 4 ? kTY2fS : kTY2dS) * (kBlock / kWave));
         }
         L.ntz = 1;
         L.ntiles = L.ntx * L.nty;
-        L.tpw = std::max(1, std::min(kTpwMax2D, div_up(L.ntiles, kWGTarget2D)));
+        L.tpw = ch.shape >= 0 ? ch.tpw : std::max(1, std::min(kTpwMax2D, div_up(L.ntiles, kWGTarget2D)));
+        L.tpw = std::min(L.tpw, L.ntiles);
         L.grid = div_up(L.ntiles, L.tpw);
     } else {
         // planes per tile: a tile streams its planes one after another, so
@@ -179,6 +278,8 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
                 }
             }
             L.tile_z = best_tz;
+            const ShapeChoice ch = shape_choice(3, L.s, L.n);
+            if (ch.tile_z > 0) L.tile_z = ch.tile_z;
         }
         L.ntz = div_up((int)p->nz, L.tile_z);
         L.ntiles = L.ntx * L.nty * L.ntz;
@@ -318,6 +419,14 @@ int Engine::init(hipStream_t st, std::string *err)
     // of a small pass is spent on the device, not in the launch call.
     const char *g = std::getenv("RN_GRAPHS");
     use_graph_ = g && g[0] == '1';
+    const char *pe = std::getenv("RN_PERSIST");
+    persist_ = !(pe && pe[0] == '0');
+    if (persist_) use_graph_ = false;
+    ENG_TRY(hipMalloc(&d_queue_, 256 * kKinds));
+    ENG_TRY(hipMalloc(&d_err_, 256));
+    ENG_TRY(hipMemset(d_err_, 0, 256));
+    ENG_TRY(hipHostMalloc((void **)&h_err_, 256, hipHostMallocDefault));
+    std::memset(h_err_, 0, 256);
     ENG_TRY(hipMalloc(&d_scal_, sizeof(Scalars) * kSlots));
     ENG_TRY(hipMalloc(&d_tabf_, sizeof(PassArgs<float>) * 2 * kSlots));
     ENG_TRY(hipMalloc(&d_tabd_, sizeof(PassArgs<double>) * 2 * kSlots));
@@ -344,17 +453,30 @@ void Engine::destroy()
     (void)hipHostFree(h_tabf_);
     (void)hipHostFree(h_tabd_);
     (void)hipHostFree(h_cnt_);
+    (void)hipFree(d_err_);
+    (void)hipFree(d_queue_);
+    d_queue_ = nullptr;
+    (void)hipHostFree(h_err_);
+    d_err_ = h_err_ = nullptr;
     for (int k = 0; k < kKinds; ++k) {
         (void)hipFree(d_blk_[k]);
         (void)hipHostFree(h_blk_[k]);
     }
     for (auto e : ev_chunk_)
         if (e) (void)hipEventDestroy(e);
+    for (auto &v : tev_) {
+        for (auto e : v) (void)hipEventDestroy(e);
+        v.clear();
+    }
     d_scal_ = nullptr;
 }
 
-int Engine::prepare(Net *net, hipStream_t st, std::string *err)
+// Setup runs on the side stream when the context has one (its own compute
+// stream is in use): the upload, validation and connectivity kernels of a new
+// network then overlap the pass launches of the running ones.
+int Engine::prepare(Net *net, hipStream_t st_compute, std::string *err)
 {
+    const hipStream_t st = side_ ? side_ : st_compute;
     const rn_problem *p = &net->prob;
     const Layout &L = net->L;
     char *base = net->base;
@@ -420,6 +542,7 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.tpw = L.tpw;
         A.grid = L.grid;
         A.groups = L.groups;
+        A.round0 = net->round0;
         for (int d = 0; d < 3; ++d) {
             A.g64[d] = net->gd[d];
             A.gT[d] = d < p->dim ? (const T *)(base + L.off_gT) + (size_t)d * n : nullptr;
@@ -464,15 +587,17 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
         net->res.Q_in = net->res.Q_out = net->res.G = G;
         net->res.K = G * (double)(net->na - 1) / cross_section(p);
         net->status = RN_OK;
+        // outputs of the setup alone (complete: the host has seen its event)
+        const hipStream_t so = side_ ? side_ : st;
+        ENG_TRY(hipEventRecord(net->ev_c, so));
+        ENG_TRY(hipEventRecord(net->ev_d, so));
         if (p->p_out)
             ENG_TRY(hipMemcpyAsync(p->p_out, base + L.off_P, 8 * n,
-                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, so));
         if (p->mask_out)
             ENG_TRY(hipMemcpyAsync(p->mask_out, base + L.off_mask, n,
-                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
-        ENG_TRY(hipEventRecord(net->ev_c, st));
-        ENG_TRY(hipEventRecord(net->ev_d, st));
-        ENG_TRY(hipEventRecord(net->ev, st));
+                                   p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, so));
+        ENG_TRY(hipEventRecord(net->ev, so));
         by_slot_[net->slot] = nullptr;
         free_slots_.push_back(net->slot);
         net->slot = -1;
@@ -496,6 +621,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
     init.bhat = 1.0;
     init.last_check = INFINITY;
     const int par0 = (int)(rounds_ & 1);
+    net->round0 = rounds_;   // the network's first pass runs in the next round
     if (L.s == 4) {
         float *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (float *)(base + L.off_gT) + (size_t)k * n;
@@ -515,7 +641,6 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
     }
     ENG_TRY(hipMemcpyAsync(ds, &init, sizeof(Scalars), hipMemcpyHostToDevice, st));
     ENG_TRY(hipEventRecord(net->ev_c, st));
-    net->round0 = rounds_;
     net->kind = kind_of(net);
     net->first_chunk = chunk_seq_ + 1;
     net->prev_est = -1.0;
@@ -568,6 +693,37 @@ int Engine::rebuild(hipStream_t st, std::string *err)
     return RN_OK;
 }
 
+void Engine::set_timing(bool on)
+{
+    timing_ = on;
+    if (on)
+        for (int k = 0; k < kKinds; ++k) {
+            kind_s_[k] = 0.0;
+            kind_n_[k] = 0;
+        }
+}
+
+// Record the next timing event of the chunk being launched; kind < 0 marks
+// the chunk's first event (before any launch).
+int Engine::record_timing(int kind, hipStream_t st, std::string *err)
+{
+    std::vector<hipEvent_t> &ev = tev_[tmirror_];
+    if (kind < 0) {
+        trec_ = 0;
+        tkind_[tmirror_].clear();
+    } else {
+        tkind_[tmirror_].push_back(kind);
+    }
+    if ((int)ev.size() <= trec_) {
+        hipEvent_t e = nullptr;
+        ENG_TRY(hipEventCreate(&e));
+        ev.push_back(e);
+    }
+    ENG_TRY(hipEventRecord(ev[trec_], st));
+    ++trec_;
+    return RN_OK;
+}
+
 // Plain launches of `rounds` pass rounds (no rounds_ bookkeeping).
 int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
 {
@@ -581,6 +737,31 @@ int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
                 ENG_TRY(launch_pass<float>(dim, d_tabf_, blk, d_scal_, nblk_[k], par, single_[k], st));
             else
                 ENG_TRY(launch_pass<double>(dim, d_tabd_, blk, d_scal_, nblk_[k], par, single_[k], st));
+            if (recording_) {
+                int r = record_timing(k, st, err);
+                if (r) return r;
+            }
+        }
+    }
+    return RN_OK;
+}
+
+// One persistent launch per kind runs all `rounds` rounds of its networks.
+int Engine::launch_persistent(int rounds, hipStream_t st, std::string *err)
+{
+    for (int k = 0; k < kKinds; ++k) {
+        if (!nblk_[k]) continue;
+        const int dim = kind_dim(k);
+        const uint2 *blk = single_[k] >= 0 ? nullptr : d_blk_[k];
+        if (!kind_fp64(k))
+            ENG_TRY(launch_pass_persist<float>(dim, d_tabf_, blk, d_scal_, nblk_[k], rounds_, rounds, single_[k],
+                                               d_err_, d_queue_ + 32 * k, st));
+        else
+            ENG_TRY(launch_pass_persist<double>(dim, d_tabd_, blk, d_scal_, nblk_[k], rounds_, rounds, single_[k],
+                                                d_err_, d_queue_ + 32 * k, st));
+        if (recording_) {
+            int r = record_timing(k, st, err);
+            if (r) return r;
         }
     }
     return RN_OK;
@@ -622,6 +803,7 @@ int Engine::launch_chunk(int rounds, hipStream_t st, std::string *err)
     peak_active_ = std::max(peak_active_, (int)active_.size());
     int kinds = 0;
     for (int k = 0; k < kKinds; ++k) kinds += nblk_[k] ? 1 : 0;
+    tkind_[next_mirror_].clear();
     if (use_graph_ && rounds >= kGraphRounds) {
         // whole graphs only: the chunk is rounded up to a multiple of the
         // graph's (even) round count, so every replay starts on its parity
@@ -633,15 +815,28 @@ int Engine::launch_chunk(int rounds, hipStream_t st, std::string *err)
         for (int i = 0; i < reps; ++i) ENG_TRY(hipGraphLaunch(gexec_, st));
         rounds = reps * kGraphRounds;
     } else {
-        int r = launch_rounds(rounds, st, err);
+        // with timing on, events bracket every launch of this chunk
+        recording_ = timing_;
+        tmirror_ = next_mirror_;
+        tkind_[tmirror_].clear();
+        if (recording_) {
+            int r = record_timing(-1, st, err);
+            if (r) {
+                recording_ = false;
+                return r;
+            }
+        }
+        int r = persist_ ? launch_persistent(rounds, st, err) : launch_rounds(rounds, st, err);
+        recording_ = false;
         if (r) return r;
     }
     rounds_ += rounds;
-    launches_ += (int64_t)rounds * kinds;
+    launches_ += persist_ ? (int64_t)kinds : (int64_t)rounds * kinds;
     int hi = 0;
     for (Net *n : active_) hi = std::max(hi, n->slot + 1);
     const int b = next_mirror_;
     ENG_TRY(hipMemcpyAsync(h_scal_[b], d_scal_, sizeof(Scalars) * hi, hipMemcpyDeviceToHost, st));
+    if (persist_) ENG_TRY(hipMemcpyAsync(h_err_ + 16 * b, d_err_, 8 * sizeof(unsigned), hipMemcpyDeviceToHost, st));
     ENG_TRY(hipEventRecord(ev_chunk_[b], st));
     mirror_hi_[b] = hi;
     mirror_seq_[b] = ++chunk_seq_;
@@ -657,6 +852,22 @@ int Engine::collect(std::vector<Net *> *finished, bool all, hipStream_t st, std:
         const int b = outstanding_.front();
         outstanding_.pop_front();
         ENG_TRY(hipEventSynchronize(ev_chunk_[b]));
+        if (persist_ && h_err_[16 * b] != 0) {
+            const unsigned *e = h_err_ + 16 * b;
+            if (err)
+                *err = "persistent pass kernel: a wait for a network's previous pass exceeded its bound (slot " +
+                       std::to_string(e[1]) + ", passes needed " + std::to_string(e[2]) + ", seen " +
+                       std::to_string(e[3]) + ", mode " + std::to_string(e[4]) + ", round " + std::to_string(e[5]) +
+                       " of the launch, table entry " + std::to_string(e[6]) + ")";
+            return RN_EDEVICE;
+        }
+        for (size_t i = 0; i < tkind_[b].size(); ++i) {
+            float ms = 0.f;
+            ENG_TRY(hipEventElapsedTime(&ms, tev_[b][i], tev_[b][i + 1]));
+            kind_s_[tkind_[b][i]] += 1e-3 * (double)ms;
+            kind_n_[tkind_[b][i]] += 1;
+        }
+        tkind_[b].clear();
         const int in_flight = outstanding_.empty() ? 0 : mirror_rounds_[outstanding_.front()];
         double min_remain = 1e30;
         int64_t min_iters = INT64_MAX;
@@ -705,6 +916,7 @@ void Engine::abort_all()
     gexec_ = nullptr;
     active_.clear();
     outstanding_.clear();
+    for (auto &v : tkind_) v.clear();
     free_slots_.clear();
     for (int s = kSlots - 1; s >= 0; --s) free_slots_.push_back(s);
     for (auto &b : by_slot_) b = nullptr;
@@ -735,9 +947,14 @@ int Engine::finalize(Net *net, const Scalars &h, hipStream_t st, std::string *er
     const double *P_final = (const double *)(base + L.off_P) + (size_t)(h.refreshes & 1) * n;
     const hipMemcpyKind kd = p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
     ENG_TRY(hipEventRecord(net->ev_d, st));
-    if (p->p_out) ENG_TRY(hipMemcpyAsync(p->p_out, P_final, 8 * n, kd, st));
-    if (p->mask_out) ENG_TRY(hipMemcpyAsync(p->mask_out, base + L.off_mask, n, kd, st));
-    ENG_TRY(hipEventRecord(net->ev, st));
+    // the output copies wait for every launch issued so far (the network's
+    // last pass may be in a chunk still in flight) and then run on the side
+    // stream, so that copies to host memory do not hold up the next chunk
+    const hipStream_t so = (side_ && (p->p_out || p->mask_out)) ? side_ : st;
+    if (so != st) ENG_TRY(hipStreamWaitEvent(so, net->ev_d, 0));
+    if (p->p_out) ENG_TRY(hipMemcpyAsync(p->p_out, P_final, 8 * n, kd, so));
+    if (p->mask_out) ENG_TRY(hipMemcpyAsync(p->mask_out, base + L.off_mask, n, kd, so));
+    ENG_TRY(hipEventRecord(net->ev, so));
     by_slot_[net->slot] = nullptr;
     free_slots_.push_back(net->slot);
     net->slot = -1;

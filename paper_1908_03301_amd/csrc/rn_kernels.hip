@@ -38,6 +38,10 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
+#include <stddef.h>
+
 namespace rn {
 
 // ---------------------------------------------------------------- helpers
@@ -60,6 +64,29 @@ __device__ __forceinline__ double ld_through(const double *p)
 __device__ __forceinline__ void st_through(double *p, double v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Loads and stores of the CG state. Between launches (COH = false) plain
+// accesses suffice: a kernel boundary makes every store visible. Inside a
+// persistent launch (COH = true) a pass reads what other workgroups, on other
+// XCDs with their own L2s, wrote in the previous pass, and its own XCD's L2
+// may still hold the buffer from two passes back: the state then moves by
+// device-scope accesses (global_load / global_store with sc1), which write
+// through the L2 and do not return a line another XCD has since written.
+// The bonds, the mask and the FP64 conductances are read-only during the
+// iterations and keep plain loads.
+template <bool COH, typename T>
+__device__ __forceinline__ T ldc(const T *p)
+{
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+
+template <bool COH, typename T>
+__device__ __forceinline__ void stc(T *p, T v)
+{
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
 }
 
 // Workgroup index -> tile index so that each XCD (workgroups are dealt to the
@@ -225,6 +252,10 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
 // waiting for a chain of memory round trips after the reduction.
 constexpr int kScalWords = (int)(sizeof(Scalars) / 8);
 static_assert(sizeof(Scalars) % 8 == 0 && kScalWords <= kBlock, "control block words");
+constexpr int kModeWord = (int)(offsetof(Scalars, mode) / 8);
+static_assert(offsetof(Scalars, mode) == 0, "mode is the low half of the first control block word");
+constexpr int kPassesWord = (int)(offsetof(Scalars, passes) / 8);
+static_assert(offsetof(Scalars, passes) % 8 == 0 && kModeWord != kPassesWord, "control block words");
 
 __device__ __forceinline__ unsigned long long prefetch_scalars(const Scalars *s)
 {
@@ -240,6 +271,11 @@ __device__ __forceinline__ unsigned long long prefetch_scalars(const Scalars *s)
 // on the top counter. Device-scope atomics on one address are serviced one
 // after another, so a single counter for a 2048-workgroup pass queued 2048
 // atomics at the end of every pass.
+// COH (persistent launches): every wave first waits for its own state stores
+// to complete, so that a workgroup counts only once its tile is in memory, and
+// the last workgroup publishes the control block with device-scope stores,
+// the pass count last (the word later passes of the same network wait on).
+template <bool COH>
 __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tickets, Scalars *s, int lb, int grid,
                             int groups, int mode, unsigned long long spre)
 {
@@ -248,6 +284,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     __shared__ unsigned long long sl[kScalWords];
     constexpr int kStride = kTicketStride / (int)sizeof(unsigned);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if constexpr (COH) __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int k = 0; k < kRed; ++k) {
         double v = wave_sum(acc[k]);
@@ -304,7 +341,17 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
         else step_after_refresh(ls, t);
     }
     __syncthreads();
-    if (threadIdx.x < kScalWords) reinterpret_cast<unsigned long long *>(s)[threadIdx.x] = sl[threadIdx.x];
+    unsigned long long *sw = reinterpret_cast<unsigned long long *>(s);
+    if constexpr (COH) {
+        const int t = (int)threadIdx.x;
+        if (t < kScalWords && t != kPassesWord)
+            __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (t == kPassesWord) __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        if (threadIdx.x < kScalWords) sw[threadIdx.x] = sl[threadIdx.x];
+    }
 }
 
 // What one pass does with the direction and the FP64 field, from the control
@@ -352,7 +399,7 @@ __device__ __forceinline__ double with_steps(double P, double sa2, double p2, do
 // issued before any branch on its data: two memory round trips per node, and
 // few enough registers that the rare refresh does not lower the occupancy of
 // the CG pass that shares its kernel.
-template <typename T, int DIM>
+template <typename T, int DIM, bool COH>
 __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
                                              double *__restrict__ Pd, int x, int y, int z, const Step<T> &k_,
                                              double sigma_next, bool bonly, double (&acc)[kRed])
@@ -389,19 +436,19 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
         gd[2 * k + 1] = has[2 * k + 1] ? gdp : 0.0;
     }
     if (!live) {
-        Pd[i] = Ps[i];
+        stc<COH>(Pd + i, ldc<COH>(Ps + i));
         return;
     }
     // batch 2: the node's and its neighbours' pressures and directions
-    const double Pi = Ps[i];
-    const T pi_ = k_.p1[i], pi2_ = k_.p2[i];
+    const double Pi = ldc<COH>(Ps + i);
+    const T pi_ = ldc<COH>(k_.p1 + i), pi2_ = ldc<COH>(k_.p2 + i);
     double Pn[2 * DIM];
     T pn_[2 * DIM], pn2_[2 * DIM];
 #pragma unroll
     for (int e = 0; e < 2 * DIM; ++e) {
-        Pn[e] = Ps[jn[e]];
-        pn_[e] = k_.p1[jn[e]];
-        pn2_[e] = k_.p2[jn[e]];
+        Pn[e] = ldc<COH>(Ps + jn[e]);
+        pn_[e] = ldc<COH>(k_.p1 + jn[e]);
+        pn2_[e] = ldc<COH>(k_.p2 + jn[e]);
     }
     // bonly: evaluate b = b - A 0, the interior pressures taken as 0 and the
     // inlet face at 1 (the first refresh of a solve)
@@ -429,10 +476,10 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     else dT = diag_sum(gb[0], gb[1], gb[2], gb[3], gb[4], gb[5]);
     const T rs = (T)(r64 / sigma_next);
     const T zs = dT > T(0) ? apply_minv(rs, dT, a.jacobi != 0) : T(0);
-    Pd[i] = bonly ? Pi : pi;
-    a.dst.z[i] = zs;
-    k_.p0[i] = pi_;
-    a.dst.u[i] = T(0);
+    stc<COH>(Pd + i, bonly ? Pi : pi);
+    stc<COH>(a.dst.z + i, zs);
+    stc<COH>(k_.p0 + i, pi_);
+    stc<COH>(a.dst.u + i, T(0));
     acc[0] += r64 * r64;
     acc[1] += (double)rs * (double)zs;
     acc[2] += pi * r64;
@@ -468,7 +515,7 @@ struct Tile2D {
     static constexpr int COLS = kWave * SEG;                                          // columns per workgroup
 };
 
-template <typename T, int SHAPE>
+template <typename T, int SHAPE, bool COH>
 __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int yb, int lane,
                                           int w, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
@@ -524,8 +571,9 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
             for (int sg = 0; sg < SEG; ++sg) {
                 const int64_t i = (int64_t)rowc(yy) * nx + xc[sg];
-                const double v = with_steps(P[i], k.sa2, (double)p2s[i], k.sa, (double)ps[i]);
-                if (valid[sg] && yy < ny) P[i] = v;
+                const double v = with_steps(ldc<COH>(P + i), k.sa2, (double)ldc<COH>(p2s + i), k.sa,
+                                            (double)ldc<COH>(ps + i));
+                if (valid[sg] && yy < ny) stc<COH>(P + i, v);
             }
         }
     }
@@ -539,9 +587,9 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
             const int64_t i = ro + xc[sg];
-            z_[sg][j] = zs[i];
-            u_[sg][j] = us[i];
-            p_[sg][j] = ps[i];
+            z_[sg][j] = ldc<COH>(zs + i);
+            u_[sg][j] = ldc<COH>(us + i);
+            p_[sg][j] = ldc<COH>(ps + i);
             gxv[sg][j] = gx[i];
             gyv[sg][j + 1] = gy[i];
         }
@@ -555,8 +603,8 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
             for (int sg = 0; sg < SEG; ++sg) {
                 const int64_t i = ro + xc[sg];
-                Pv[sg][j] = P[i];
-                p2_[sg][j] = k.sa2 != 0.0 ? p2s[i] : T(0);   // none pending right after a refresh
+                Pv[sg][j] = ldc<COH>(P + i);
+                p2_[sg][j] = k.sa2 != 0.0 ? ldc<COH>(p2s + i) : T(0);   // none pending right after a refresh
             }
         }
     }
@@ -580,7 +628,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
             const int64_t i = ro + xc[sg];
-            const T z0 = zs[i], u0 = us[i], p0 = ps[i];
+            const T z0 = ldc<COH>(zs + i), u0 = ldc<COH>(us + i), p0 = ldc<COH>(ps + i);
             if (hrow && lv[sg]) {
                 ez[sg] = z0;
                 eu[sg] = u0;
@@ -596,7 +644,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     T hz = T(0), hu = T(0), hp = T(0), hg = T(0);
     {
         const int64_t i = hok ? (int64_t)(y0 + hr_) * nx + hx : 0;
-        const T z0 = zs[i], u0 = us[i], p0 = ps[i], g0 = gx[i];
+        const T z0 = ldc<COH>(zs + i), u0 = ldc<COH>(us + i), p0 = ldc<COH>(ps + i), g0 = gx[i];
         if (hok) {
             hz = z0;
             hu = u0;
@@ -670,10 +718,10 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             if (ok) {
                 const int64_t i = (int64_t)yy * nx + x;
                 if (!kFieldFirst && flush)
-                    P[i] = with_steps(Pv[sg][j], k.sa2, (double)p2_[sg][j], k.sa, (double)p_[sg][j]);
-                zd[i] = zc;
-                pd[i] = pc;
-                ud[i] = uv;
+                    stc<COH>(P + i, with_steps(Pv[sg][j], k.sa2, (double)p2_[sg][j], k.sa, (double)p_[sg][j]));
+                stc<COH>(zd + i, zc);
+                stc<COH>(pd + i, pc);
+                stc<COH>(ud + i, uv);
             }
             const double dq = (double)qv, du = (double)uv;
             const double dp = (double)pc, dz = live ? (double)zc : 0.0;
@@ -723,11 +771,11 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
                 const int x = x0 + kWave * sg + lane;
                 if (x < a.nx)
                     for (int yy = y0; yy < y1; ++yy)
-                        refresh_node<T, 2>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
+                        refresh_node<T, 2, false>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
             }
         }
         // (a rare pass: the control block is read here, not held through the refresh)
-        finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, prefetch_scalars(s));
+        finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, prefetch_scalars(s));
         return;
     }
     const unsigned long long spre = prefetch_scalars(s);
@@ -739,9 +787,9 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         const int x0 = tx * Tile2D<T, SHAPE>::COLS;
         const int yb = ty * Tile2D<T, SHAPE>::ROWS;
-        cg2d_tile<T, SHAPE>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
+        cg2d_tile<T, SHAPE, false>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
     }
-    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
 }
 
 // ---------------------------------------------------------------- 3D pass
@@ -772,7 +820,7 @@ struct Bond3 {                 // bonds of one plane for this thread's rows
     T yh;                      // bond from the row above this wave's first row
 };
 
-template <typename T>
+template <typename T, bool COH>
 __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int y0, int z0,
                                           int z1, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
@@ -845,23 +893,23 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const int64_t i = rowoff[j] + zo;
-            R.z[j] = zs[i];
-            R.u[j] = us[i];
-            R.p[j] = ps[i];
+            R.z[j] = ldc<COH>(zs + i);
+            R.u[j] = ldc<COH>(us + i);
+            R.p[j] = ldc<COH>(ps + i);
         }
         if (flush && ring) {           // a plane this tile stores: its FP64 field
 #pragma unroll
             for (int j = 0; j < kRows; ++j) {
                 const int64_t i = rowoff[j] + zo;
-                R.P[j] = P[i];
-                R.p2[j] = p2s[i];
+                R.P[j] = ldc<COH>(P + i);
+                R.p2[j] = ldc<COH>(p2s + i);
             }
         }
         if (ring) {
             const int64_t i = hoff + zo;
-            R.hz = zs[i];
-            R.hu = us[i];
-            R.hp = ps[i];
+            R.hz = ldc<COH>(zs + i);
+            R.hu = ldc<COH>(us + i);
+            R.hp = ldc<COH>(ps + i);
         }
     };
     auto load_bonds = [&](Bond3<T> &G, int zz) {
@@ -905,8 +953,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvc[j] = ok ? z_ : T(0);
             if (ok) {
                 const int64_t i = rowoff[j] + (int64_t)z0 * sz;
-                if (flush) P[i] = with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]);
-                zd[i] = z_;
+                if (flush) stc<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                stc<COH>(zd + i, z_);
             }
             lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
         }
@@ -928,8 +976,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvn[j] = ok ? z_ : T(0);
             if (ok && nin) {
                 const int64_t i = rowoff[j] + (int64_t)zn * sz;
-                if (flush) P[i] = with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]);
-                zd[i] = z_;
+                if (flush) stc<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                stc<COH>(zd + i, z_);
             }
             if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];
         }
@@ -960,8 +1008,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             const T uv = live ? apply_minv(qv, d, jacobi) : T(0);
             if (rok[j]) {
                 const int64_t i = rowoff[j] + (int64_t)zc * sz;
-                pd[i] = p0;
-                ud[i] = uv;
+                stc<COH>(pd + i, p0);
+                stc<COH>(ud + i, uv);
             }
             const double dp = (double)p0, dq = (double)qv, du = (double)uv;
             const double dz = live ? (double)zvc[j] : 0.0;
@@ -1008,7 +1056,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
         const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
         const int z1 = min(z0 + a.tile_z, a.nz);
         if (mode == MODE_CG) {
-            cg3d_tile<T>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, st, acc);
+            cg3d_tile<T, false>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, st, acc);
         } else {
             const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
             const double sigma_next = s->sigma_next;
@@ -1019,11 +1067,251 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
                     const int yy = y0 + w * kRows + j;
                     if (yy >= a.ny) break;
                     for (int zz = z0; zz < z1; ++zz)
-                        refresh_node<T, 3>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
+                        refresh_node<T, 3, false>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
                 }
         }
     }
-    finish_pass(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+}
+
+// ---------------------------------------------------------------- persistent pass kernels
+// One launch runs `rounds` pass rounds of every network in the block table:
+// item it = r * nblk + j is round r of table entry j (network, local block).
+// Workgroups claim items in increasing order from a queue counter (one
+// atomic per item, the next one claimed while the current one runs). Before
+// an item of round r a workgroup waits until its network has completed the
+// passes of the rounds before (its control block's pass count, which the
+// network's last workgroup publishes after everything else of the pass,
+// reaches round - round0) or has finished. An item waits only on items of
+// lower index, and every item of lower index has been claimed by a
+// workgroup that is running: the lowest unfinished item's workgroup is
+// running it (anything it claimed before is finished), and nothing it waits
+// on is unfinished. So the launch drains whatever other kernels occupy the
+// GPU and however many of its workgroups are resident. Every wait is still
+// bounded: past kSpinTicks, or once another wait has given up, the workgroup
+// sets *err and skips the item, so every wave ends normally and the host
+// reports the error. A network's passes run the same tile code and the same
+// reduction as in the single-round kernels, so its results are bit-identical
+// to theirs.
+constexpr uint64_t kSpinTicks = 200000000ull;   // 2 s of the 100 MHz s_memrealtime clock
+
+// err[0] = 1 once a wait gave up; the first to give up records what it saw
+// in err[1..6]: network slot, passes needed, passes seen, mode seen, round
+// and table entry of its item.
+__device__ __forceinline__ int await_pass(const Scalars *s, int64_t need, unsigned *err, unsigned slot,
+                                          int round, int entry)
+{
+    const unsigned long long *w = reinterpret_cast<const unsigned long long *>(s);
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (true) {
+        const unsigned long long done = __hip_atomic_load(w + kPassesWord, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long mw = __hip_atomic_load(w + kModeWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int)(uint32_t)mw == MODE_DONE) return 1;   // finished: the item is skipped
+        if ((int64_t)done >= need) return 1;
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0;
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kSpinTicks) {
+            unsigned expected = 0u;
+            if (__hip_atomic_compare_exchange_strong(err, &expected, 1u, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)) {
+                const unsigned info[6] = {slot, (unsigned)need, (unsigned)done, (unsigned)(uint32_t)mw,
+                                          (unsigned)round, (unsigned)entry};
+                for (int k = 0; k < 6; ++k)
+                    __hip_atomic_store(err + 1 + k, info[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Wait for the item's network, then load its control block into LDS (one
+// 8-byte word per thread, device-scope loads). Returns the word this thread
+// holds (for finish_pass) and whether the item runs.
+__device__ __forceinline__ bool begin_item(Scalars *s, int64_t need, unsigned *err, int it_parity,
+                                           unsigned long long (&snap)[kScalWords], int (&go)[2],
+                                           unsigned long long &spre, unsigned slot, int round, int entry)
+{
+    if (threadIdx.x == 0) go[it_parity] = await_pass(s, need, err, slot, round, entry);
+    __syncthreads();
+    if (!go[it_parity]) return false;
+    const unsigned long long *w = reinterpret_cast<const unsigned long long *>(s);
+    const int t = threadIdx.x < kScalWords ? (int)threadIdx.x : 0;
+    const unsigned long long v = __hip_atomic_load(w + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    spre = threadIdx.x < kScalWords ? v : 0ull;
+    if (threadIdx.x < kScalWords) snap[threadIdx.x] = spre;
+    __syncthreads();
+    return reinterpret_cast<const Scalars *>(snap)->mode != MODE_DONE;
+}
+
+// The item's control-block fields as wave-uniform values (read from the LDS
+// snapshot and made scalar with readfirstlane), so that they live in SGPRs and
+// branches on them stay uniform, as with the scalar loads of the one-round
+// kernels.
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t rfl(int64_t v)
+{
+    const uint32_t lo = (uint32_t)rfl((int)(uint32_t)v), hi = (uint32_t)rfl((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double rfl(double v) { return __longlong_as_double(rfl((int64_t)__double_as_longlong(v))); }
+
+__device__ __forceinline__ Scalars uniform_scalars(const Scalars *sv)
+{
+    Scalars u;
+    u.mode = rfl(sv->mode);
+    u.first = rfl(sv->first);
+    u.flush = rfl(sv->flush);
+    u.refreshes = rfl(sv->refreshes);
+    u.passes = rfl(sv->passes);
+    u.sigma = rfl(sv->sigma);
+    u.sigma_next = rfl(sv->sigma_next);
+    u.alpha = rfl(sv->alpha);
+    u.alpha2 = rfl(sv->alpha2);
+    u.beta = rfl(sv->beta);
+    return u;
+}
+
+// The queue: thread 0 claims an item index (an atomic on the launch's
+// counter) into claim[], which the barriers of the item publish to the
+// workgroup. The first claim is made before the loop; inside the loop the
+// claim of the next item (claim[p ^ 1]) is issued at the start of the current
+// one, so its latency overlaps the item's work, and read after the item.
+__device__ __forceinline__ int64_t first_claim(unsigned long long *queue, unsigned long long (&claim)[2])
+{
+    if (threadIdx.x == 0) claim[0] = __hip_atomic_fetch_add(queue, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return (int64_t)claim[0];
+}
+
+__device__ __forceinline__ int64_t next_claim(unsigned long long (&claim)[2], int itp)
+{
+    __syncthreads();                      // thread 0's claim of the next item is in LDS
+    const int64_t v = (int64_t)claim[itp ^ 1];
+    __syncthreads();                      // read by all before claim[itp ^ 1] is reused
+    return v;
+}
+
+template <typename T, int SHAPE>
+__global__ __launch_bounds__(kBlock) void pass2d_persist(const PassArgs<T> *__restrict__ tab,
+                                                         const uint2 *__restrict__ blk, Scalars *scal, int nblk,
+                                                         int64_t round_base, int rounds, int slot, unsigned *err,
+                                                         unsigned long long *queue)
+{
+    __shared__ unsigned long long snap[kScalWords];
+    __shared__ int go[2];
+    __shared__ unsigned long long claim[2];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t total = (int64_t)rounds * nblk;
+    int itp = 0;
+    for (int64_t it = first_claim(queue, claim); it < total; it = next_claim(claim, itp), itp ^= 1) {
+        if (threadIdx.x == 0) claim[itp ^ 1] = __hip_atomic_fetch_add(queue, 1ull, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+        const int r = (int)(it / nblk);
+        const int j = (int)(it - (int64_t)r * nblk);
+        const uint2 e = blk ? blk[j] : make_uint2((unsigned)slot, (unsigned)j);
+        const int parity = (int)((round_base + r) & 1);
+        const PassArgs<T> &a = tab[2 * e.x + parity];
+        Scalars *s = scal + e.x;
+        unsigned long long spre = 0;
+        if (!begin_item(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
+        const Scalars u = uniform_scalars(reinterpret_cast<const Scalars *>(snap));
+        const Scalars *sv = &u;
+        const int mode = sv->mode;
+        const int lb = (int)e.y;
+        double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        const int first = xcd_remap(lb, a.grid);
+        const int m = (int)(sv->refreshes & 1);
+        const Step<T> st = make_step(a, sv);
+        if (mode != MODE_CG) {
+            const double sigma_next = sv->sigma_next;
+            const bool bonly = sv->first == 1;
+            for (int k = 0; k < a.tpw; ++k) {
+                const int tile = first + k * a.grid;
+                if (tile >= a.ntiles) break;
+                const int tx = tile % a.ntx, ty = tile / a.ntx;
+                const int x0 = tx * Tile2D<T, SHAPE>::COLS;
+                const int y0 = ty * Tile2D<T, SHAPE>::ROWS + w * Tile2D<T, SHAPE>::TY;
+                const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
+                for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
+                    const int x = x0 + kWave * sg + lane;
+                    if (x < a.nx)
+                        for (int yy = y0; yy < y1; ++yy)
+                            refresh_node<T, 2, true>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
+                }
+            }
+        } else {
+            const T alpha = (T)sv->alpha, beta = (T)sv->beta;
+            for (int k = 0; k < a.tpw; ++k) {
+                const int tile = first + k * a.grid;
+                if (tile >= a.ntiles) break;
+                if (k > 0) __syncthreads();          // the previous tile's LDS rows are reused
+                const int tx = tile % a.ntx, ty = tile / a.ntx;
+                cg2d_tile<T, SHAPE, true>(a, a.P[m], tx * Tile2D<T, SHAPE>::COLS, ty * Tile2D<T, SHAPE>::ROWS, lane,
+                                          w, alpha, beta, st, acc);
+            }
+        }
+        finish_pass<true>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void pass3d_persist(const PassArgs<T> *__restrict__ tab,
+                                                         const uint2 *__restrict__ blk, Scalars *scal, int nblk,
+                                                         int64_t round_base, int rounds, int slot, unsigned *err,
+                                                         unsigned long long *queue)
+{
+    __shared__ unsigned long long snap[kScalWords];
+    __shared__ int go[2];
+    __shared__ unsigned long long claim[2];
+    const int64_t total = (int64_t)rounds * nblk;
+    int itp = 0;
+    for (int64_t it = first_claim(queue, claim); it < total; it = next_claim(claim, itp), itp ^= 1) {
+        if (threadIdx.x == 0) claim[itp ^ 1] = __hip_atomic_fetch_add(queue, 1ull, __ATOMIC_RELAXED,
+                                                                        __HIP_MEMORY_SCOPE_AGENT);
+        const int r = (int)(it / nblk);
+        const int j = (int)(it - (int64_t)r * nblk);
+        const uint2 e = blk ? blk[j] : make_uint2((unsigned)slot, (unsigned)j);
+        const int parity = (int)((round_base + r) & 1);
+        const PassArgs<T> &a = tab[2 * e.x + parity];
+        Scalars *s = scal + e.x;
+        unsigned long long spre = 0;
+        if (!begin_item(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
+        const Scalars u = uniform_scalars(reinterpret_cast<const Scalars *>(snap));
+        const Scalars *sv = &u;
+        const int mode = sv->mode;
+        const int lb = (int)e.y;
+        double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        const int tile = xcd_remap(lb, a.grid);
+        const int m = (int)(sv->refreshes & 1);
+        const Step<T> st = make_step(a, sv);
+        if (tile < a.ntiles) {
+            const int tx = tile % a.ntx;
+            const int ty = (tile / a.ntx) % a.nty;
+            const int tz = tile / (a.ntx * a.nty);
+            const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
+            const int z1 = min(z0 + a.tile_z, a.nz);
+            if (mode == MODE_CG) {
+                cg3d_tile<T, true>(a, a.P[m], x0, y0, z0, z1, (T)sv->alpha, (T)sv->beta, st, acc);
+            } else {
+                const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+                const double sigma_next = sv->sigma_next;
+                const bool bonly = sv->first == 1;
+                const int x = x0 + lane;
+                if (x < a.nx)
+                    for (int jj = 0; jj < kRows; ++jj) {
+                        const int yy = y0 + w * kRows + jj;
+                        if (yy >= a.ny) break;
+                        for (int zz = z0; zz < z1; ++zz)
+                            refresh_node<T, 3, true>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
+                    }
+            }
+        } else {
+            // an idle workgroup of the padded grid still reaches the reduction;
+            // the 3D tile's LDS is reused by the next item after its barriers
+        }
+        finish_pass<true>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    }
 }
 
 // ---------------------------------------------------------------- setup kernels
@@ -1155,7 +1443,8 @@ __global__ void uf_flags_kernel(Lat L, const double *ga, int *parent, unsigned *
 
 // Mask byte, initial pressure field (faces 1 / 0, dead nodes 1 when tied to
 // the inlet only, live nodes the CG's initial guess: the linear profile
-// 1 - c_axis / (n_axis - 1) when `linear`, else 0) and the live count.
+// 1 - c_axis / (n_axis - 1) when `linear`, else 0; not written when P is
+// null) and the live count.
 __global__ void mask_final_kernel(Lat L, int *parent, const unsigned *flags, uint8_t *mask, double *P,
                                   unsigned long long *n_live, int linear)
 {
@@ -1184,7 +1473,7 @@ __global__ void mask_final_kernel(Lat L, int *parent, const unsigned *flags, uin
             }
         }
         mask[i] = m;
-        P[i] = p0;
+        if (P) P[i] = p0;
     }
     cnt = (unsigned long long)wave_sum((double)cnt);
     if ((threadIdx.x & (kWave - 1)) == 0 && cnt) atomicAdd(n_live, cnt);
@@ -1246,6 +1535,35 @@ __global__ void direct_flux_kernel(Lat L, const double *ga, double *out)
     }
 }
 
+__global__ void clear_u64_kernel(unsigned long long *p, int n)
+{
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+// Conductances of the launch-shape trials: values in [1, 2) from a
+// multiplicative hash of the entry index (no zero, so every node is live).
+__global__ void fill_trial_kernel(double *g, int64_t n, uint32_t salt)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t h = ((uint32_t)i ^ salt) * 2654435761u;
+        g[i] = 1.0 + (double)(h >> 8) * (1.0 / 16777216.0);
+    }
+}
+
+hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    fill_trial_kernel<<<(int)(b < 1 ? 1 : b), kBlock, 0, st>>>(g, n, salt);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st)
+{
+    clear_u64_kernel<<<1, kWave, 0, st>>>(p, n);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- host launchers
 
 static inline int grid_for(int64_t n)
@@ -1300,6 +1618,58 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
     return hipGetLastError();
 }
 
+// Workgroups of one persistent launch: as many as the kernel's occupancy
+// keeps resident on all CUs at once (more would only queue behind them).
+template <typename T>
+static hipError_t persist_capacity(int dim, int *cap)
+{
+    static int cached[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    const int fi = sizeof(T) == 8 ? 1 : 0, di = dim == 2 ? 0 : (dim == -2 ? 1 : 2);
+    if (cached[fi][di]) {
+        *cap = cached[fi][di];
+        return hipSuccess;
+    }
+    int dev = 0, cus = 0, per = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (dim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 0>, kBlock, 0);
+    else if (dim == -2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 1>, kBlock, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass3d_persist<T>, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if (per < 1 || cus < 1) return hipErrorInvalidConfiguration;
+    cached[fi][di] = per * cus;
+    *cap = cached[fi][di];
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_pass_persist(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks,
+                               int64_t round_base, int rounds, int slot, unsigned *err, unsigned long long *queue,
+                               hipStream_t st)
+{
+    if (nblocks <= 0 || rounds <= 0) return hipSuccess;
+    int cap = 0;
+    hipError_t e = persist_capacity<T>(dim, &cap);
+    if (e != hipSuccess) return e;
+    const int64_t items = (int64_t)nblocks * rounds;
+    const int grid = (int)std::min<int64_t>(items, (int64_t)cap);
+    // the queue counter starts at 0 (a kernel, not a memset node)
+    e = launch_clear_u64(queue, 1, st);
+    if (e != hipSuccess) return e;
+    if (dim == 2)
+        pass2d_persist<T, 0><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+    else if (dim == -2)
+        pass2d_persist<T, 1><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+    else
+        pass3d_persist<T><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+    return hipGetLastError();
+}
+
+template hipError_t launch_pass_persist<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int64_t,
+                                               int, int, unsigned *, unsigned long long *, hipStream_t);
+template hipError_t launch_pass_persist<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int64_t,
+                                                int, int, unsigned *, unsigned long long *, hipStream_t);
 template hipError_t launch_scale<float>(const Lat &, const double *const[3], const uint8_t *, float *const[3],
                                         float *, int64_t, hipStream_t);
 template hipError_t launch_scale<double>(const Lat &, const double *const[3], const uint8_t *, double *const[3],

@@ -62,6 +62,30 @@ struct Layout {
 };
 Layout make_layout(const rn_problem *p, const rn_opts *o);
 
+// ------------------------------------------------------------------ launch-shape table
+// The launch shape of a network's pass kernel by size class (floor(log2 of
+// its node count)), dimension and inner precision: the 2D tile (0 full, 1
+// small) and tiles per workgroup, the 3D tile depth. It is process-wide and
+// changes only when a table is installed (rn_autotune, rn_tune_load,
+// rn_tune_reset), so a network's shape, hence its arithmetic, never depends on
+// the other networks it runs with. An entry with shape < 0 (2D) or tile_z == 0
+// (3D) follows the built-in rules of make_layout.
+struct ShapeChoice {
+    int shape = -1, tpw = 0, tile_z = 0;
+    double ns_per_node = 0.0;   // measured device time per node and pass (0: not measured)
+};
+constexpr int kShapeClasses = 32;
+struct ShapeTable {
+    ShapeChoice c[2][2][kShapeClasses];   // [dim - 2][inner FP32 ? 1 : 0][class]
+};
+int shape_class(int64_t n);
+ShapeChoice shape_choice(int dim, int s, int64_t n);
+ShapeTable shape_table_get();
+void shape_table_install(const ShapeTable &t);
+bool shape_choice_valid(int dim, const ShapeChoice &c);
+int shape_table_parse(const std::string &text, ShapeTable *out);   // RN_OK or RN_EINVAL
+std::string shape_table_format(const ShapeTable &t);
+
 // ------------------------------------------------------------------ one network
 enum NetPhase { NET_NEW, NET_PREPARING, NET_ACTIVE, NET_FINISHING, NET_DONE };
 
@@ -120,6 +144,15 @@ public:
     int peak_active() const { return peak_active_; }
     // forget every network (after a device error): slots, tables, mirrors
     void abort_all();
+    // stream for setup and output copies (nullptr: everything on the compute stream)
+    void set_side(hipStream_t s) { side_ = s; }
+    // per-launch device timing of the pass kernels (events between launches)
+    void set_timing(bool on);
+    double kind_seconds(int k) const { return kind_s_[k]; }
+    int64_t kind_launches(int k) const { return kind_n_[k]; }
+    // kind -> (RN_PATH_*, precision RN_FP64 / RN_MIXED)
+    static int kind_path(int k) { return (k == 1 || k == 3) ? RN_PATH_3D : (k >= 4 ? RN_PATH_2D_SMALL : RN_PATH_2D_FULL); }
+    static int kind_precision(int k) { return kind_fp64(k) ? RN_FP64 : RN_MIXED; }
 
 private:
     int kind_of(const Net *n) const
@@ -165,7 +198,23 @@ private:
     hipGraphExec_t gexec_ = nullptr;
     int graph_parity_ = -1;
     int launch_rounds(int rounds, hipStream_t st, std::string *err);
+    int launch_persistent(int rounds, hipStream_t st, std::string *err);
     int capture(hipStream_t st, std::string *err);
+    // persistent launches: `rounds` pass rounds of a kind in one launch
+    // (RN_PERSIST=0 falls back to one launch per round and kind)
+    bool persist_ = true;
+    hipStream_t side_ = nullptr;
+    unsigned *d_err_ = nullptr, *h_err_ = nullptr;   // a bounded wait gave up (device word, pinned mirror)
+    unsigned long long *d_queue_ = nullptr;          // item counters of the persistent launches, 256 B per kind
+    // timing: events of the chunk behind mirror b, tev_[b][0] before its first
+    // launch and tev_[b][i + 1] after launch i, whose kind is tkind_[b][i]
+    bool timing_ = false, recording_ = false;
+    std::vector<hipEvent_t> tev_[2];
+    std::vector<int> tkind_[2];
+    int trec_ = 0, tmirror_ = 0;
+    double kind_s_[kKinds] = {};
+    int64_t kind_n_[kKinds] = {};
+    int record_timing(int kind, hipStream_t st, std::string *err);
 };
 
 }  // namespace rn
@@ -178,6 +227,8 @@ struct rn_ctx {
     size_t budget = 0;
     hipStream_t own = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;     // the context's second stream: setup and output copies of networks
+                                    // (used while the context runs on its own stream)
     std::string err;
     rn::Pool pool;
     rn::Engine engine;

@@ -46,8 +46,9 @@ def test_strerror_and_defaults(lib):
 
 def test_struct_layout_matches_header(lib):
     # sizes of the three ABI structs, compiled from rn.h by the host compiler
-    src = '#include "rn.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu",sizeof(rn_problem),' \
-          'sizeof(rn_opts),sizeof(rn_result));return 0;}\n'
+    src = '#include "rn.h"\n#include <stdio.h>\n#include <stddef.h>\nint main(){printf("%zu %zu %zu %zu %zu",' \
+          'sizeof(rn_problem),sizeof(rn_opts),sizeof(rn_result),sizeof(rn_stats_t),' \
+          'offsetof(rn_stats_t,pass_timed_launches));return 0;}\n'
     import subprocess
     import tempfile
     with tempfile.TemporaryDirectory() as d:
@@ -55,7 +56,8 @@ def test_struct_layout_matches_header(lib):
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), os.path.join(d, "t.c"), "-o",
                                os.path.join(d, "t")])
         out = subprocess.check_output([os.path.join(d, "t")]).decode().split()
-    assert [int(v) for v in out] == [C.sizeof(B.rn_problem), C.sizeof(B.rn_opts), C.sizeof(B.rn_result)]
+    assert [int(v) for v in out] == [C.sizeof(B.rn_problem), C.sizeof(B.rn_opts), C.sizeof(B.rn_result),
+                                     C.sizeof(B.rn_stats_t), B.rn_stats_t.pass_timed_launches.offset]
 
 
 def test_plan_struct_and_paths(lib):
@@ -221,6 +223,7 @@ def test_batch_and_serve_argument_checks(lib):
     assert lib.rn_submit(None, C.byref(_prob().c), None, C.byref(t)) == B.RN_EINVAL
     assert lib.rn_poll(None, 1, C.byref(B.rn_result())) == B.RN_EINVAL
     assert lib.rn_stats(None, C.byref(B.rn_stats_t())) == B.RN_EINVAL
+    assert lib.rn_set_timing(None, 1) == B.RN_EINVAL
 
 
 def test_fbm_entry_points_reject_bad_arguments(lib):
@@ -232,3 +235,43 @@ def test_fbm_entry_points_reject_bad_arguments(lib):
     DA3 = C.c_void_p * 3
     g = DA3(x.ctypes.data, x.ctypes.data, None)
     assert L.rn_fbm_bonds(None, 2, 4, 4, 1, p, 1.0, 0, None, 1.0, C.byref(g), B.RN_MEM_HOST) == B.RN_EINVAL
+
+
+def test_launch_shape_table_load_and_reset(lib, tmp_path):
+    """rn_tune_load installs a launch-shape table that rn_plan follows for the
+    classes it sets (and only those); malformed files are refused whole;
+    rn_tune_reset restores the built-in rules."""
+    n512 = B.problem(dim=2, nx=512, ny=512, nz=1, axis=0, g=[np.ones((512, 512)), np.ones((512, 512))])
+    n800 = B.problem(dim=2, nx=800, ny=800, nz=1, axis=0, g=[np.ones((800, 800)), np.ones((800, 800))])
+    n64c = B.problem(dim=3, nx=64, ny=64, nz=64, axis=0, g=[np.ones((64, 64, 64))] * 3)
+    mixed = B.opts(B.RN_MIXED)
+    base512 = B.rn_plan(n512, mixed)
+    base512d = B.rn_plan(n512, B.opts(B.RN_FP64))
+    base800 = B.rn_plan(n800, mixed)
+    base3d = B.rn_plan(n64c, mixed)
+    assert base512["path"] == B.RN_PATH_2D_FULL and base512["tiles_per_wg"] == 1
+    f = tmp_path / "shapes.txt"
+    # 512^2 = 2^18 nodes: class 18; 64^3 = 2^18: class 18
+    f.write_text("# comment\n2 fp32 18 1 2 0 0.125\n3 fp32 18 0 0 8 0.5\n")
+    try:
+        B.rn_tune_load(str(f))
+        p = B.rn_plan(n512, mixed)
+        assert p["path"] == B.RN_PATH_2D_SMALL and p["tiles_per_wg"] == 2
+        assert p["workgroups"] >= p["tiles"] // 2
+        assert B.rn_plan(n800, mixed) == base800          # 800^2 is in class 19: untouched
+        assert B.rn_plan(n512, B.opts(B.RN_FP64)) == base512d     # FP64 entries untouched
+        assert B.rn_plan(n64c, mixed)["tile_z"] == 8
+        for bad in ("2 fp32 18 1 9 0 0.1\n", "4 fp32 18 1 1 0 0.1\n", "2 fp16 18 1 1 0 0.1\n",
+                    "2 fp32 40 1 1 0 0.1\n", "3 fp32 18 0 0 0 0.1\n", "2 fp32 18 1 1 0\n", "2 fp32 18 1 1 0 0.1 x\n"):
+            f.write_text(bad)
+            with pytest.raises(B.RNError):
+                B.rn_tune_load(str(f))
+            # a refused file leaves the installed table alone
+            assert B.rn_plan(n512, mixed)["path"] == B.RN_PATH_2D_SMALL
+        with pytest.raises(B.RNError):
+            B.rn_tune_load(str(tmp_path / "missing.txt"))
+    finally:
+        B.rn_tune_reset()
+    assert B.rn_plan(n512, mixed) == base512
+    assert B.rn_plan(n64c, mixed) == base3d
+    assert lib.rn_autotune(None, None, 0) == B.RN_EINVAL

@@ -229,3 +229,47 @@ def test_graph_replay_bit_identical(solos):
             assert P.tobytes() == P_solo.tobytes()
     finally:
         c.close()
+
+
+def test_host_input_admitted_mid_run(ctx):
+    """A request with host buffers, submitted while a large device-resident network
+    iterates, is uploaded and prepared on the context's side stream, overlaps the
+    running passes, finishes first, and gives the bits of its solo solve."""
+    import torch
+    big = I.fbm_network(2, 1536, 1536, 1, H=0.7, sigma=1.5, occupancy=0.62, index=810)
+    small = I.fbm_network(3, 60, 50, 40, H=0.7, sigma=1.0, occupancy=0.6, index=811)
+    o = B.opts(B.RN_MIXED, 1e-8)
+    gd = [torch.from_numpy(a).to("cuda") for a in big.g]
+    torch.cuda.synchronize()
+    P_small_solo = np.zeros(small.shape)
+    r_small_solo = ctx.solve(B.problem(small, p_out=P_small_solo), o)
+    r_big_solo = ctx.solve(B.problem(dim=2, nx=big.nx, ny=big.ny, nz=1, axis=0, g=gd), o)
+    c = B.Context(0)
+    try:
+        tb = c.submit(B.problem(dim=2, nx=big.nx, ny=big.ny, nz=1, axis=0, g=gd), o)
+        t0 = time.time()
+        while c.stats()["active"] < 1:
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        time.sleep(0.05)                  # the big network is iterating
+        P_small = np.zeros(small.shape)
+        ts = c.submit(B.problem(small, p_out=P_small), o)
+        done = {}
+        while len(done) < 2:
+            assert time.time() - t0 < 300, "served requests did not finish"
+            for t in (tb, ts):
+                if t not in done:
+                    st, r = c.poll(t)
+                    if st != B.RN_EAGAIN:
+                        done[t] = (st, r, time.time())
+            time.sleep(0.0005)
+    finally:
+        c.close()
+    st_s, r_s, t_s = done[ts]
+    st_b, r_b, t_b = done[tb]
+    assert st_s == B.RN_OK and st_b == B.RN_OK
+    same(r_small_solo, r_s)
+    same(r_big_solo, r_b)
+    assert P_small.tobytes() == P_small_solo.tobytes()
+    assert t_s < t_b, "the host-input request waited for the running network"
+    say(f"host-input request done in {r_s.t_total_s:.3f}s while the 1536^2 network took {r_b.t_total_s:.3f}s")
