@@ -161,6 +161,8 @@ def main():
                     help="served stream: requests submitted at once to measure the saturation rate")
     ap.add_argument("--pool", type=int, default=32, help="served stream: distinct networks generated for it")
     ap.add_argument("--cpu-sample", type=int, default=16, help="batch512: members the CPU oracle solves")
+    ap.add_argument("--shapes", choices=("search", "builtin"), default="search",
+                    help="batch512: launch shapes from rn_autotune run before the timed batches, or the built-in rules")
     ap.add_argument("--batch-size", type=int, default=512, help="batch512: networks in the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
@@ -416,7 +418,22 @@ def batch_bench(args, B, I, np):
     sample of the members in worker processes while the GPU comparison legs
     run.
     """
+    import tempfile
     import torch
+    shapes = {"source": "built-in rules"}
+    if args.shapes == "search":
+        # the launch-shape search of every size class (untimed, like a warmup)
+        c = B.Context(0)
+        path = os.path.join(tempfile.mkdtemp(prefix="rn_shapes_"), "shapes.txt")
+        t = time.perf_counter()
+        c.autotune(path)
+        c.close()
+        rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+        shapes = {"source": "rn_autotune on this device before the timed batches",
+                  "search_s": round(time.perf_counter() - t, 2),
+                  "table": [" ".join(r) for r in rows]}
+        print(f"[bench] launch-shape search: {len(rows)} classes in {shapes['search_s']} s", file=sys.stderr,
+              flush=True)
     specs = I.batch_specs(args.batch_size)
     nets = generate(_gen_batch, specs, "batch")
     gd = [[torch.from_numpy(a).to("cuda") for a in n.g] for n in nets]
@@ -456,12 +473,14 @@ def batch_bench(args, B, I, np):
               "nodes_2d": int(sum(n.n for n in nets if n.dim == 2)),
               "nodes_3d": int(sum(n.n for n in nets if n.dim == 3)), "tol": args.tol,
               "precision": "fp32 inner CG + fp64 refresh/solution/flux", "x0": "linear profile",
-              "preconditioner": "Jacobi", "inputs": "resident in HBM"}
+              "preconditioner": "Jacobi", "inputs": "resident in HBM",
+              "launch_shapes": shapes["source"]}
     out = _contract(args, value, "solves/s", tot_m, len(walls_m), config)
     out["latency_ms"] = {"p50": round(1e3 * float(np.percentile(lat_m, 50)), 2),
                          "p99": round(1e3 * float(np.percentile(lat_m, 99)), 2),
                          "of": "completion time of each batch member from the rn_solve_batch call"}
     out["batch_wall_s"] = [round(w, 3) for w in walls_m]
+    out["launch_shapes"] = shapes
     kern = kernel_accounting(B, nets, probs, steps_m, B.RN_MIXED, st_m)
     dom_key = max(kern, key=lambda k: kern[k]["device_s"])
     dom = kern[dom_key]
