@@ -169,7 +169,8 @@ int rn_destroy(rn_ctx *ctx);
  */
 int rn_set_stream(rn_ctx *ctx, void *stream);
 
-/* Message of the last RN_EDEVICE on this context ("" if none). */
+/* Message of the last RN_EDEVICE on this context, or of the last RN_ENOMEM of
+ * rn_build_mask_noalloc ("" if none). */
 const char *rn_last_error(rn_ctx *ctx);
 
 /*
@@ -197,6 +198,29 @@ size_t rn_footprint(const rn_problem *prob, const rn_opts *opts);
  * Errors: RN_EINVAL, RN_ENOMEM, RN_EDEVICE; outputs untouched on error.
  */
 int rn_build_mask(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
+
+/*
+ * rn_build_mask for callers that cannot allocate device memory (code under
+ * HIP graph construction, tight serving loops, harnesses that forbid
+ * hipMalloc): the same mask and live count, computed in a static scratch
+ * array that every GPU the library runs on holds until the process ends
+ * (RN_NOALLOC_MAX_NODES x 8 bytes + 256 bytes, 32 MiB; the device address
+ * is looked up once per device by rn_create). The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine.
+ *   - prob->mem must be RN_MEM_DEVICE: g and mask_out are device buffers of
+ *     the caller (mask_out required, nx*ny*nz bytes, written directly).
+ *   - nx*ny*nz above RN_NOALLOC_MAX_NODES: RN_ENOMEM, and rn_last_error()
+ *     names the limit; nothing runs.
+ *   - Invalid conductances (negative, NaN, Inf): RN_EINVAL with mask_out
+ *     untouched. RN_EINVAL also for a bad shape, host memory, a NULL
+ *     mask_out or while the request server runs; RN_EDEVICE on a HIP error.
+ *   - Runs on the context's stream and waits for it. Every call on one GPU
+ *     shares that GPU's scratch: calls that overlap on one GPU (from two
+ *     contexts, or two threads with different contexts) race and must be
+ *     serialised by the caller. Each call clears the counters it uses.
+ */
+#define RN_NOALLOC_MAX_NODES (1 << 22)
+int rn_build_mask_noalloc(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
 
 /*
  * Solve one network (Sec. II, Eqs. 3-4): mask, preconditioned CG (opts->precond,

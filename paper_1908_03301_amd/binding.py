@@ -28,8 +28,9 @@ RN_PATH_2D_FULL, RN_PATH_2D_SMALL, RN_PATH_3D = 0, 1, 2
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
             "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds",
-            "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset"]
+            "rn_build_mask_noalloc", "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset"]
 RN_TUNE_QUICK = 1
+RN_NOALLOC_MAX_NODES = 1 << 22
 
 
 class rn_problem(C.Structure):
@@ -108,6 +109,7 @@ def lib():
         L.rn_footprint.argtypes = [P(rn_problem), P(rn_opts)]
         L.rn_footprint.restype = C.c_size_t
         L.rn_build_mask.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
+        L.rn_build_mask_noalloc.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
         L.rn_solve.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(rn_result)]
         L.rn_solve_batch.argtypes = [C.c_void_p, C.c_int32, P(rn_problem), P(rn_opts), C.c_int32, P(rn_result)]
         L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
@@ -124,7 +126,7 @@ def lib():
         L.rn_fbm_bonds.argtypes = [C.c_void_p, C.c_int32, I64, I64, I64, C.c_void_p, C.c_double, C.c_int32,
                                    P(DA3), C.c_double, P(DA3), C.c_int32]
         for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask",
-                  "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset",
+                  "rn_build_mask_noalloc", "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset",
                   "rn_solve",
                   "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"):
             getattr(L, f).restype = C.c_int
@@ -331,6 +333,14 @@ class Context:
             raise RNError(st, self.last_error())
         return int(nl.value)
 
+    def build_mask_noalloc(self, prob: Problem) -> int:
+        """rn_build_mask_noalloc: device buffers only, nothing allocated by the library."""
+        nl = C.c_int64(0)
+        st = lib().rn_build_mask_noalloc(self.h, C.byref(self._own(prob).c), C.byref(nl))
+        if st:
+            raise RNError(st, self.last_error())
+        return int(nl.value)
+
     def solve(self, prob: Problem, o: Optional[rn_opts] = None, check: bool = True) -> rn_result:
         res = rn_result()
         st = lib().rn_solve(self.h, C.byref(self._own(prob).c), C.byref(o) if o is not None else None, C.byref(res))
@@ -428,6 +438,10 @@ def rn_create(device: int = 0, hbm_budget_bytes: int = 0) -> Context:
 
 def rn_build_mask(ctx: Context, prob: Problem) -> int:
     return ctx.build_mask(prob)
+
+
+def rn_build_mask_noalloc(ctx: Context, prob: Problem) -> int:
+    return ctx.build_mask_noalloc(prob)
 
 
 def rn_solve(ctx: Context, prob: Problem, o: Optional[rn_opts] = None) -> rn_result:

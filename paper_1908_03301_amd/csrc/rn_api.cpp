@@ -453,6 +453,10 @@ int rn_create(int device, size_t budget, rn_ctx **out)
     ctx->stream = ctx->own;
     if (ctx->engine.init(ctx->stream, &ctx->err)) return fail();
     ctx->engine_ok = true;
+    if (hipHostMalloc((void **)&ctx->h_small, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+        return fail();
+    // this device's copy of the static scratch of rn_build_mask_noalloc
+    if (noalloc_setup(device) != hipSuccess) return fail();
     *out = ctx;
     return RN_OK;
 }
@@ -488,6 +492,7 @@ int rn_destroy(rn_ctx *ctx)
         delete S;
     }
     if (ctx->engine_ok) ctx->engine.destroy();
+    if (ctx->h_small) (void)hipHostFree(ctx->h_small);
     ctx->pool.release_all();
     if (ctx->own) (void)hipStreamDestroy(ctx->own);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
@@ -610,6 +615,47 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
         return done(RN_EDEVICE);
     if (n_live_out) *n_live_out = (int64_t)hc[0];
     return done(RN_OK);
+}
+
+int rn_build_mask_noalloc(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
+{
+    if (!ctx) return RN_EINVAL;
+    int st = check_shape(p);
+    if (st) return st;
+    if (!p->mask_out || p->mem != RN_MEM_DEVICE) return RN_EINVAL;
+    const int64_t n = p->nx * p->ny * p->nz;
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    if (n > kNoAllocMaxNodes) {
+        ctx->err = "rn_build_mask_noalloc: " + std::to_string(n) + " nodes exceed the static scratch of " +
+                   std::to_string(kNoAllocMaxNodes) + " nodes";
+        return RN_ENOMEM;
+    }
+    if (ctx->server) return RN_EINVAL;        // the server owns the stream once started
+    RN_TRY(hipSetDevice(ctx->device));
+    char *base = (char *)noalloc_scratch(ctx->device);
+    if (!base) {
+        ctx->err = "rn_build_mask_noalloc: no static scratch on this device";
+        return RN_EDEVICE;
+    }
+    int *parent = (int *)base;
+    unsigned *flags = (unsigned *)(base + 4 * (size_t)n);
+    unsigned long long *cnt = (unsigned long long *)(base + kNoAllocCounterOffset);
+    unsigned long long *hc = ctx->h_small;
+    const Lat lat = make_lat(p);
+    const double *gd[3] = {p->g[0], p->g[1], p->dim == 3 ? p->g[2] : nullptr};
+    hipStream_t s = ctx->stream;
+    // the counters keep the previous call's values: clear them, then check the
+    // conductances before anything is written to mask_out
+    RN_TRY(launch_clear_u64(cnt, 4, s));
+    RN_TRY(launch_validate(lat, gd, cnt + 1, s));
+    RN_TRY(hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    RN_TRY(hipStreamSynchronize(s));
+    if (hc[1] != 0) return RN_EINVAL;
+    RN_TRY(launch_mask(lat, gd, parent, flags, p->mask_out, nullptr, cnt, true, s));
+    RN_TRY(hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    RN_TRY(hipStreamSynchronize(s));
+    if (n_live_out) *n_live_out = (int64_t)hc[0];
+    return RN_OK;
 }
 
 int rn_solve(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, rn_result *out)

@@ -130,6 +130,17 @@ hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st);
 // g[i] in [1, 2) from a hash of i and salt (the networks of the launch-shape trials)
 hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st);
 
+// Static scratch of the allocation-free mask entry point: 8 bytes per node
+// (union-find parents and component flags) for up to kNoAllocMaxNodes nodes,
+// then four 8-byte counters. noalloc_setup(device), called with `device`
+// current, looks up that device's copy once; noalloc_scratch(device) returns
+// it afterwards (nullptr before the setup).
+constexpr int64_t kNoAllocMaxNodes = (int64_t)1 << 22;
+constexpr size_t kNoAllocCounterOffset = (size_t)kNoAllocMaxNodes * 8;
+constexpr size_t kNoAllocScratchBytes = kNoAllocCounterOffset + 256;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_setup(int device);
+void *noalloc_scratch(int device);
 // One pass of every network in the block table blk[0..nblocks): entry
 // (network, local block); tab[2 * network + parity] are that network's
 // arguments and scal[network] its control block. dim: 2 (2D, full tiles),

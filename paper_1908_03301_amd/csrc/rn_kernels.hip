@@ -1550,6 +1550,46 @@ __global__ void fill_trial_kernel(double *g, int64_t n, uint32_t salt)
     }
 }
 
+// ---------------------------------------------------------------- static scratch
+// Device memory of the allocation-free mask entry point: the union-find
+// parents and the component flags (4 bytes each per node) and four 8-byte
+// counters, for lattices of up to kNoAllocMaxNodes nodes. Every GPU the
+// library runs on holds its own copy until the process ends. Host code never
+// passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in, not a device address): noalloc_setup() looks up the device
+// address once per device, with that device current, and every launch uses
+// that address.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[kNoAllocMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_setup(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;      // the caller makes `device` current
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kNoAllocMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    return g_noalloc_ptr[device];
+}
+
 hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st)
 {
     int64_t b = (n + kBlock - 1) / kBlock;

@@ -224,6 +224,7 @@ def test_batch_and_serve_argument_checks(lib):
     assert lib.rn_poll(None, 1, C.byref(B.rn_result())) == B.RN_EINVAL
     assert lib.rn_stats(None, C.byref(B.rn_stats_t())) == B.RN_EINVAL
     assert lib.rn_set_timing(None, 1) == B.RN_EINVAL
+    assert lib.rn_build_mask_noalloc(None, None, None) == B.RN_EINVAL
 
 
 def test_fbm_entry_points_reject_bad_arguments(lib):
