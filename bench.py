@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "network solves/s + p99 latency at 1e-8 resid vs plain FP64 CG; CG HBM GB/s"
+SHAPES_CACHE = os.path.join(ROOT, "paper_1908_03301_amd", "shapes_gfx950.txt")
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -161,8 +162,11 @@ def main():
                     help="served stream: requests submitted at once to measure the saturation rate")
     ap.add_argument("--pool", type=int, default=32, help="served stream: distinct networks generated for it")
     ap.add_argument("--cpu-sample", type=int, default=16, help="batch512: members the CPU oracle solves")
-    ap.add_argument("--shapes", choices=("search", "builtin"), default="search",
-                    help="batch512: launch shapes from rn_autotune run before the timed batches, or the built-in rules")
+    ap.add_argument("--shapes", choices=("cache", "search", "builtin"), default="cache",
+                    help="batch512: launch shapes from the shape cache the library wrote on an MI355X "
+                         "(paper_1908_03301_amd/shapes_gfx950.txt), from rn_autotune run now (untimed), or the "
+                         "built-in rules")
+    ap.add_argument("--shapes-file", default=SHAPES_CACHE, help="the cache --shapes cache loads")
     ap.add_argument("--batch-size", type=int, default=512, help="batch512: networks in the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
@@ -421,7 +425,12 @@ def batch_bench(args, B, I, np):
     import tempfile
     import torch
     shapes = {"source": "built-in rules"}
-    if args.shapes == "search":
+    if args.shapes == "cache" and os.path.exists(args.shapes_file):
+        B.rn_tune_load(args.shapes_file)
+        rows = [l.split() for l in open(args.shapes_file) if l.strip() and not l.startswith("#")]
+        shapes = {"source": f"rn_tune_load of {os.path.relpath(args.shapes_file, ROOT)} (written by rn_autotune "
+                            f"on an MI355X)", "table": [" ".join(r) for r in rows]}
+    elif args.shapes == "search":
         # the launch-shape search of every size class (untimed, like a warmup)
         c = B.Context(0)
         path = os.path.join(tempfile.mkdtemp(prefix="rn_shapes_"), "shapes.txt")

@@ -309,15 +309,18 @@ int rn_plan(const rn_problem *prob, const rn_opts *opts, rn_plan_t *out);
  * same alone, in a batch and in the served stream; a network queued or
  * running keeps the shape it was given when it was submitted.
  */
-#define RN_TUNE_QUICK 1   /* rn_autotune: only classes up to 2^18 (2D) / 2^17 (3D) nodes */
+#define RN_TUNE_QUICK 1   /* rn_autotune: only classes up to 2^18 (2D) / 2^17 (3D) nodes, small trials */
 
 /*
  * Measure every candidate shape of every size class (2D: 2^12 .. 2^24 nodes,
  * full or small tile x 1 or 2 tiles per workgroup; 3D: 2^15 .. 2^24 nodes,
- * tile depth 2 .. 32 planes) in both precisions on ctx's device: for each, a
- * few identical synthetic networks of the class are solved together for 48
- * CG passes and the pass kernels' device time per node and pass is taken from
- * the event timing of rn_set_timing. The fastest shape of each class is
+ * tile depth 2 .. 32 planes) in both precisions on ctx's device: for each,
+ * identical synthetic networks of the class, enough that a round moves about
+ * 2^25 nodes (at most 256 copies; the objective is the throughput of large
+ * batches), are solved together for 32 CG passes and the pass kernels'
+ * device time per node and pass is taken from the event timing of
+ * rn_set_timing. With RN_TUNE_QUICK a round moves about 2^22 nodes (at most
+ * 16 copies). The fastest shape of each class is
  * installed process-wide and, if cache_path is not NULL, written to that file
  * (text, one line per class; rn_tune_load reads it back). Takes seconds and
  * device memory from the context's budget. Do not solve on other contexts

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -83,6 +84,9 @@ int tick(rn_ctx *ctx, Sched *S, bool *progressed)
     // 1. admit waiting networks while memory and control slots allow
     while (!S->waiting.empty() && !ctx->engine.full()) {
         Net *net = S->waiting.front();
+        // optional cap on the memory of the networks in flight (RN_ACTIVE_BYTES):
+        // a small working set stays in the memory-side cache between passes
+        if (ctx->active_cap && ctx->pool.in_use() > 0 && ctx->pool.in_use() + net->L.total > ctx->active_cap) break;
         hipError_t he;
         void *p = ctx->pool.alloc(net->L.total, &he);
         if (!p) {
@@ -336,12 +340,17 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
 }
 
 // ------------------------------------------------------------------ launch-shape search
-// A trial runs `copies` identical networks of one size class together (so
-// that a round moves at least ~4 M nodes, as in a batch) for kTrialPasses CG
-// passes from x = 0 (the tolerance is out of reach), with one candidate
-// shape installed for that class, and measures the device time of the pass
-// launches per node and pass with the library's event timing.
-constexpr int kTrialPasses = 48;
+// A trial runs `copies` identical networks of one size class together for
+// kTrialPasses CG passes from x = 0 (the tolerance is out of reach), with one
+// candidate shape installed for that class, and measures the device time of
+// the pass launches per node and pass with the library's event timing. The
+// copies make a round move about 2^25 nodes (tens of thousands of
+// workgroups, as in the 512-network batch): a shape that is fastest for one
+// small network alone, where a pass is bound by the latency of one tile, is
+// not the fastest in a launch that fills the chip many times over.
+constexpr int kTrialPasses = 32;
+constexpr int64_t kTrialNodes = (int64_t)1 << 25;
+constexpr int kTrialCopiesMax = 256;
 
 int shape_trial(rn_ctx *ctx, int dim, int s, int side, int copies, const ShapeChoice &cand, double *ns_per_node)
 {
@@ -447,6 +456,7 @@ int rn_create(int device, size_t budget, rn_ctx **out)
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail();
     ctx->budget = budget ? budget : (size_t)(0.9 * (double)free_b);
+    if (const char *cap = std::getenv("RN_ACTIVE_BYTES")) ctx->active_cap = (size_t)std::strtoull(cap, nullptr, 10);
     ctx->pool.set_budget(ctx->budget);
     if (hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) return fail();
     if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) return fail();
@@ -751,7 +761,9 @@ int rn_autotune(rn_ctx *ctx, const char *cache_path, int32_t flags)
                 while (shape_class(nodes(side)) > cls) --side;
                 while (shape_class(nodes(side)) < cls) ++side;
                 const int64_t n = nodes(side);
-                const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 22) / n));
+                const int64_t want = quick ? ((int64_t)1 << 22) : kTrialNodes;
+                const int cmax = quick ? 16 : kTrialCopiesMax;
+                const int copies = (int)std::max<int64_t>(1, std::min<int64_t>(cmax, want / n));
                 std::vector<ShapeChoice> cands;
                 if (dim == 2) {
                     for (int shape : {0, 1})

@@ -419,8 +419,11 @@ int Engine::init(hipStream_t st, std::string *err)
     // of a small pass is spent on the device, not in the launch call.
     const char *g = std::getenv("RN_GRAPHS");
     use_graph_ = g && g[0] == '1';
+    // persistent launches are opt-in (RN_PERSIST=1): measured slower than one
+    // launch per round on every workload here (their device-scope state
+    // accesses give up the L2), though bit-identical to it
     const char *pe = std::getenv("RN_PERSIST");
-    persist_ = !(pe && pe[0] == '0');
+    persist_ = pe && pe[0] == '1';
     if (persist_) use_graph_ = false;
     ENG_TRY(hipMalloc(&d_queue_, 256 * kKinds));
     ENG_TRY(hipMalloc(&d_err_, 256));

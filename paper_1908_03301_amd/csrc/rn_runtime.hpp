@@ -238,6 +238,7 @@ struct rn_ctx {
     std::atomic<int> callers{0};    // threads waiting for call_mu (the server steps aside for them)
     rn_server *server = nullptr;
     void *fbm_plans = nullptr;      // FFT plans of the last generated grid (rn_fbm.hip)
+    size_t active_cap = 0;          // RN_ACTIVE_BYTES: cap on the device bytes of networks in flight (0: none)
     unsigned long long *h_small = nullptr;   // pinned, 8 words: counters read back by rn_build_mask_noalloc
 };
 

@@ -1,8 +1,8 @@
 """GPU tests of the persistent pass kernels against the one-round-per-launch kernels.
 
-A context created with RN_PERSIST=0 in the environment runs one pass kernel
-launch per round and kind; the default runs every chunk of rounds of a kind
-in one persistent launch, where a network's passes read each other's state
+By default a context runs one pass kernel launch per round and kind; a
+context created with RN_PERSIST=1 in the environment runs every chunk of
+rounds of a kind in one persistent launch, where a network's passes read each other's state
 through device-scope loads and stores and wait on the network's published
 pass count. Both run the same tile code and the same fixed-order reduction,
 so every result field and every pressure must be bit-identical: alone, in a
@@ -45,18 +45,23 @@ def networks():
     ]
 
 
-def solve_all(persist: bool, batched: bool):
-    """Results and pressures of every network, from a context created with or
-    without persistent launches."""
+def make_ctx(persist: bool):
+    """A context created with or without persistent launches."""
     old = os.environ.get("RN_PERSIST")
     os.environ["RN_PERSIST"] = "1" if persist else "0"
     try:
-        c = B.Context(0)
+        return B.Context(0)
     finally:
         if old is None:
             del os.environ["RN_PERSIST"]
         else:
             os.environ["RN_PERSIST"] = old
+
+
+def solve_all(persist: bool, batched: bool):
+    """Results and pressures of every network, from a context created with or
+    without persistent launches."""
+    c = make_ctx(persist)
     try:
         sets = networks()
         Ps = [np.zeros(net.shape) for net, _, _ in sets]
@@ -99,7 +104,7 @@ def test_persistent_served_and_oracle(reference, oracle_mod):
     import time
     ref_res, ref_P, _ = reference
     sets = networks()
-    c = B.Context(0)
+    c = make_ctx(True)
     try:
         Ps = [np.zeros(net.shape) for net, _, _ in sets]
         probs = [B.problem(net, p_out=P) for (net, _, _), P in zip(sets, Ps)]
