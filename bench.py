@@ -50,7 +50,7 @@ MULTI = {
     "serve": "served request stream, Poisson arrivals at 0.7 x the measured batched saturation rate; nodes "
              "log-uniform in [1e4, 3e7], 2D/3D 50/50, FBM ln g (H=0.75, sigma=1.5), occupancy U(0.3,1), "
              "flow along x; requests cycle through a pre-generated seeded pool",
-    "aniso": "permeability anisotropy study (Eq. 2, Fig. 10): 2D 512x512 FBM ln g (sigma=1.5) with "
+    "aniso": "permeability anisotropy study (Eq. 2, Fig. 10): 2D 512x512 FBM ln g (sigma from --sigma) with "
              "beta_x/beta_y in {1,2,4,8,16} and H in {0.75,0.35}, 16 networks each, K_x and K_y of every "
              "network in one batch",
     "fbmgen": "network generation (Eqs. 1-2, Table I's task): FBM node field by Fourier filtering, bonds and "
@@ -169,6 +169,7 @@ def main():
     ap.add_argument("--shapes-file", default=SHAPES_CACHE, help="the cache --shapes cache loads")
     ap.add_argument("--batch-size", type=int, default=512, help="batch512: networks in the batch")
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--sigma", type=float, default=1.5, help="aniso: spread sigma of ln g")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 CG comparison leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle PCG iterations in the CPU sample")
@@ -312,9 +313,10 @@ def _gen_batch(spec):
     return I.batch_network(spec)
 
 
-def _gen_aniso(spec):
+def _gen_aniso(job):
     from paper_1908_03301_amd import inputs as I
-    return I.aniso_network(spec)
+    spec, sigma = job
+    return I.aniso_network(spec, sigma=sigma)
 
 
 def _gen_stream(req):
@@ -611,7 +613,7 @@ def aniso_bench(args, B, I, np):
     (H, beta_x / beta_y) is the quantity of Fig. 10."""
     import torch
     specs = I.aniso_specs()
-    nets = generate(_gen_aniso, specs, "aniso")
+    nets = generate(_gen_aniso, [(sp, args.sigma) for sp in specs], "aniso")
     gd = [[torch.from_numpy(a).to("cuda") for a in n.g] for n in nets]
     torch.cuda.synchronize()
     probs = [B.problem(dim=2, nx=n.nx, ny=n.ny, nz=1, axis=ax, g=g) for n, g in zip(nets, gd) for ax in (0, 1)]
@@ -636,7 +638,7 @@ def aniso_bench(args, B, I, np):
     summary = {key: {"min": round(min(v), 3), "median": round(float(np.median(v)), 3), "max": round(max(v), 3),
                      "networks": len(v)} for key, v in table.items()}
     out = _contract(args, value, "solves/s", sum(walls), len(walls),
-                    {"workload": MULTI["aniso"], "networks": len(nets), "solves": len(probs),
+                    {"workload": MULTI["aniso"], "sigma": args.sigma, "networks": len(nets), "solves": len(probs),
                      "nodes": sum(n.n for n in nets), "tol": args.tol,
                      "precision": "fp32 inner CG + fp64 refresh/solution/flux", "inputs": "resident in HBM"})
     out["Kx_over_Ky"] = summary

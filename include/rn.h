@@ -254,7 +254,9 @@ int rn_solve_batch(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn
  * Serving: queue one network for solving and return at once with a ticket.
  * The first call starts the context's server thread, which admits queued
  * networks as device memory (the HBM budget, per rn_footprint) and control
- * slots allow, runs every admitted network in the same pass launches
+ * slots allow (in arrival order; when the oldest waiting network does not fit
+ * the memory free now, later ones that fit go ahead of it, at most 8 times
+ * before it is admitted), runs every admitted network in the same pass launches
  * (continuous batching: a network joins at the next chunk boundary and leaves
  * as soon as it converges) and frees its memory at once. The buffers named
  * by prob (g, p_out, mask_out) must stay valid and unmodified until rn_poll
@@ -285,7 +287,7 @@ int rn_poll(rn_ctx *ctx, uint64_t ticket, rn_result *out);
  * in a batch or in the served stream. */
 typedef struct {
     int32_t path;          /* RN_PATH_* */
-    int32_t tiles_per_wg;  /* tiles one workgroup runs per pass (2D: 1 or 2; 3D: 1) */
+    int32_t tiles_per_wg;  /* tiles one workgroup runs per pass (2D: 1 to 4; 3D: 1) */
     int32_t tile_x, tile_y, tile_z;   /* nodes per tile along x, y, z (tile_z = 1 in 2D) */
     int32_t tiles;         /* tiles covering the lattice */
     int32_t workgroups;    /* workgroups per pass (a multiple of 8) */
@@ -313,14 +315,15 @@ int rn_plan(const rn_problem *prob, const rn_opts *opts, rn_plan_t *out);
 
 /*
  * Measure every candidate shape of every size class (2D: 2^12 .. 2^24 nodes,
- * full or small tile x 1 or 2 tiles per workgroup; 3D: 2^15 .. 2^24 nodes,
+ * the full tile with 1 to 4 tiles per workgroup or the small tile with 1 or 2; 3D: 2^15 .. 2^24 nodes,
  * tile depth 2 .. 32 planes) in both precisions on ctx's device: for each,
  * identical synthetic networks of the class, enough that a round moves about
  * 2^25 nodes (at most 256 copies; the objective is the throughput of large
- * batches), are solved together for 32 CG passes and the pass kernels'
- * device time per node and pass is taken from the event timing of
- * rn_set_timing. With RN_TUNE_QUICK a round moves about 2^22 nodes (at most
- * 16 copies). The fastest shape of each class is
+ * batches), are solved together for 64 CG passes and the pass kernels'
+ * device time per node and working pass is taken from the event timing of
+ * rn_set_timing (the faster of two runs). With RN_TUNE_QUICK a round moves
+ * about 2^22 nodes (at most 16 copies). The fastest shape of each class, or
+ * the built-in one unless the fastest beats it by 3% or more, is
  * installed process-wide and, if cache_path is not NULL, written to that file
  * (text, one line per class; rn_tune_load reads it back). Takes seconds and
  * device memory from the context's budget. Do not solve on other contexts

@@ -81,22 +81,31 @@ int tick(rn_ctx *ctx, Sched *S, bool *progressed)
     // on a caller's stream everything stays on it (the caller's work that
     // produces device inputs is ordered before the setup)
     ctx->engine.set_side(ctx->stream == ctx->own ? ctx->side : nullptr);
-    // 1. admit waiting networks while memory and control slots allow
-    while (!S->waiting.empty() && !ctx->engine.full()) {
-        Net *net = S->waiting.front();
-        // optional cap on the memory of the networks in flight (RN_ACTIVE_BYTES):
-        // a small working set stays in the memory-side cache between passes
-        if (ctx->active_cap && ctx->pool.in_use() > 0 && ctx->pool.in_use() + net->L.total > ctx->active_cap) break;
-        hipError_t he;
-        void *p = ctx->pool.alloc(net->L.total, &he);
+    // 1. admit waiting networks while memory and control slots allow. The
+    // head of the queue goes first; when it does not fit the memory free now,
+    // later requests that fit may go ahead of it (first fit), each such pass
+    // counted on the head, until it has been passed kMaxBypass times: then
+    // nothing overtakes it until it is admitted, so a large request waits for
+    // memory at most that many admissions longer than in first-in first-out.
+    constexpr int kMaxBypass = 8;
+    size_t i = 0;
+    while (i < S->waiting.size() && !ctx->engine.full()) {
+        Net *net = S->waiting[i];
+        const bool head = i == 0;
+        void *p = nullptr;
+        hipError_t he = hipSuccess;
+        // optional cap on the memory of the networks in flight (RN_ACTIVE_BYTES)
+        const bool capped = ctx->active_cap && ctx->pool.in_use() > 0 &&
+                            ctx->pool.in_use() + net->L.total > ctx->active_cap;
+        if (!capped) p = ctx->pool.alloc(net->L.total, &he);
         if (!p) {
             if (he != hipSuccess) {              // the device itself is out of memory
-                S->waiting.pop_front();
+                S->waiting.erase(S->waiting.begin() + (long)i);
                 fail_net(net, RN_ENOMEM);
                 *progressed = true;
                 continue;
             }
-            if (S->preparing.empty() && S->finishing.empty() && ctx->engine.active_count() == 0 &&
+            if (head && S->preparing.empty() && S->finishing.empty() && ctx->engine.active_count() == 0 &&
                 ctx->engine.outstanding() == 0) {
                 // nothing runs that could return memory: waiting would never end
                 S->waiting.pop_front();
@@ -104,9 +113,12 @@ int tick(rn_ctx *ctx, Sched *S, bool *progressed)
                 *progressed = true;
                 continue;
             }
-            break;                               // wait until a running network frees memory
+            if (S->waiting.front()->bypassed >= kMaxBypass) break;   // the head's turn
+            ++i;                                 // a later, smaller request may fit
+            continue;
         }
-        S->waiting.pop_front();
+        if (!head) S->waiting.front()->bypassed += 1;
+        S->waiting.erase(S->waiting.begin() + (long)i);
         net->base = (char *)p;
         int r = ctx->engine.prepare(net, st, &ctx->err);
         if (r) return r;
@@ -348,7 +360,9 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
 // workgroups, as in the 512-network batch): a shape that is fastest for one
 // small network alone, where a pass is bound by the latency of one tile, is
 // not the fastest in a launch that fills the chip many times over.
-constexpr int kTrialPasses = 32;
+constexpr int kTrialPasses = 64;
+constexpr int kTrialRepeats = 2;     // each candidate is measured this often; the fastest run counts
+constexpr double kTrialMargin = 0.97; // a candidate replaces the built-in shape only when this much faster
 constexpr int64_t kTrialNodes = (int64_t)1 << 25;
 constexpr int kTrialCopiesMax = 256;
 
@@ -399,8 +413,10 @@ int shape_trial(rn_ctx *ctx, int dim, int s, int side, int copies, const ShapeCh
                     secs += ctx->engine.kind_seconds(k);
             ctx->engine.set_timing(false);
         }
+        // per node and working pass: the launches of rounds after the copies
+        // finished (until the host notices) count in the time but do no work
         int64_t passes = 0;
-        for (const rn_result &x : res) passes = std::max(passes, x.passes);
+        for (const rn_result &x : res) passes = std::max(passes, x.iters + x.refreshes);
         if (st != RN_OK && st != RN_ENOCONV) r = st;
         else if (passes <= 0 || secs <= 0.0) r = RN_EDEVICE;
         else *ns_per_node = 1e9 * secs / ((double)passes * (double)copies * (double)n);
@@ -767,7 +783,8 @@ int rn_autotune(rn_ctx *ctx, const char *cache_path, int32_t flags)
                 std::vector<ShapeChoice> cands;
                 if (dim == 2) {
                     for (int shape : {0, 1})
-                        for (int tpw : {1, 2}) {
+                        for (int tpw : {1, 2, 3, 4}) {
+                            if (shape == 1 && tpw > 2) continue;   // the small tile is for latency, not depth
                             ShapeChoice c;
                             c.shape = shape;
                             c.tpw = tpw;
@@ -781,18 +798,53 @@ int rn_autotune(rn_ctx *ctx, const char *cache_path, int32_t flags)
                             cands.push_back(c);
                         }
                 }
+                // the shape the built-in rules give this class's trial network
+                ShapeChoice builtin;
+                {
+                    shape_table_install(ShapeTable());
+                    rn_problem bp;
+                    std::memset(&bp, 0, sizeof(bp));
+                    bp.dim = dim;
+                    bp.nx = bp.ny = side;
+                    bp.nz = dim == 3 ? side : 1;
+                    bp.mem = RN_MEM_DEVICE;
+                    rn_opts bo;
+                    rn_opts_default(&bo);
+                    bo.precision = s == 4 ? RN_MIXED : RN_FP64;
+                    const Layout BL = make_layout(&bp, &bo);
+                    if (dim == 2) {
+                        builtin.shape = BL.shape;
+                        builtin.tpw = BL.tpw;
+                    } else {
+                        builtin.tile_z = BL.tile_z;
+                    }
+                    shape_table_install(result);
+                }
                 ShapeChoice best;
-                double best_ns = 0.0;
+                double best_ns = 0.0, builtin_ns = 0.0;
                 for (const ShapeChoice &c : cands) {
                     double ns = 0.0;
-                    r = shape_trial(ctx, dim, s, side, copies, c, &ns);
+                    for (int rep = 0; rep < kTrialRepeats && !r; ++rep) {
+                        double t = 0.0;
+                        r = shape_trial(ctx, dim, s, side, copies, c, &t);
+                        if (!r && (ns == 0.0 || t < ns)) ns = t;
+                    }
                     if (r) break;
+                    const bool is_builtin = dim == 2 ? (c.shape == builtin.shape && c.tpw == builtin.tpw)
+                                                     : c.tile_z == builtin.tile_z;
+                    if (is_builtin) builtin_ns = ns;
                     if (best_ns == 0.0 || ns < best_ns) {
                         best = c;
                         best_ns = ns;
                     }
                 }
                 if (r) break;
+                // keep the built-in shape unless a candidate is clearly faster
+                // (the trials' run-to-run spread is a few percent)
+                if (builtin_ns > 0.0 && best_ns > kTrialMargin * builtin_ns) {
+                    best = builtin;
+                    best_ns = builtin_ns;
+                }
                 best.ns_per_node = best_ns;
                 result.c[dim - 2][s == 4 ? 1 : 0][cls] = best;
             }

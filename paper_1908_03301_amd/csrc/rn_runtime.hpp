@@ -108,6 +108,7 @@ struct Net {
     int status = RN_OK;
     double t_start = 0.0;           // host clock at submission
     uint64_t ticket = 0;
+    int bypassed = 0;               // admissions of later requests while this one waited at the head
     double prev_est = -1.0;
     int64_t prev_iters = 0;
     int64_t first_chunk = 0;        // first chunk whose status mirror covers this network

@@ -273,3 +273,39 @@ def test_host_input_admitted_mid_run(ctx):
     assert P_small.tobytes() == P_small_solo.tobytes()
     assert t_s < t_b, "the host-input request waited for the running network"
     say(f"host-input request done in {r_s.t_total_s:.3f}s while the 1536^2 network took {r_b.t_total_s:.3f}s")
+
+
+def test_smaller_request_goes_ahead_of_one_that_does_not_fit(ctx):
+    """First-fit admission: with one large network running and a second large one
+    waiting for its memory, a small request submitted after the second is
+    admitted beside the first and finishes before the second, with its solo bits."""
+    o = B.opts(B.RN_MIXED, 1e-8)
+    big1 = I.fbm_network(2, 1024, 1024, 1, H=0.7, sigma=1.5, occupancy=0.65, index=820)
+    big2 = I.fbm_network(2, 1024, 1024, 1, H=0.7, sigma=1.5, occupancy=0.65, index=821)
+    small = I.fbm_network(2, 200, 200, 1, H=0.7, sigma=1.5, occupancy=0.7, index=822)
+    fb = B.rn_footprint(B.problem(big1), o)
+    fs = B.rn_footprint(B.problem(small), o)
+    budget = fb + 2 * fs          # room for one large network and the small one, not two large
+    r_small_solo = ctx.solve(B.problem(small), o)
+    c = B.Context(0, hbm_budget_bytes=budget)
+    try:
+        t1 = c.submit(B.problem(big1), o)
+        t2 = c.submit(B.problem(big2), o)
+        t3 = c.submit(B.problem(small), o)
+        done, order, t0 = {}, [], time.time()
+        while len(done) < 3:
+            assert time.time() - t0 < 300
+            assert c.stats()["bytes_in_use"] <= budget
+            for t in (t1, t2, t3):
+                if t not in done:
+                    st, r = c.poll(t)
+                    if st != B.RN_EAGAIN:
+                        done[t] = (st, r)
+                        order.append(t)
+            time.sleep(0.0005)
+    finally:
+        c.close()
+    assert all(done[t][0] == B.RN_OK for t in (t1, t2, t3))
+    assert order.index(t3) < order.index(t2), order
+    same(r_small_solo, done[t3][1])
+    say(f"completion order {order} (big1={t1}, big2={t2}, small={t3})")
