@@ -155,6 +155,14 @@ int rn_opts_default(rn_opts *opts);
  * `hbm_budget_bytes` for the library's own buffers (0 = 90% of the device's
  * free memory at creation). The context owns a non-blocking stream at default
  * priority until rn_set_stream() replaces it. *out receives the handle.
+ * How pass rounds are launched is read from the environment at creation;
+ * results are bit-identical in every mode:
+ *   RN_PERSIST=1  one persistent work-queue launch per chunk of rounds and
+ *                 network kind, items claimed on all XCDs;
+ *   RN_PERSIST=2  the same with each network of a kind of small networks
+ *                 placed on one XCD (other kinds: one launch per round);
+ *   RN_GRAPHS=1   rounds replayed from a captured hipGraph;
+ *   otherwise one launch per round and kind.
  * Errors: RN_EINVAL (NULL out, bad device), RN_EDEVICE.
  */
 int rn_create(int device, size_t hbm_budget_bytes, rn_ctx **out);

@@ -45,7 +45,9 @@ struct Scalars {
     double last_check;  // true relative residual at the previous failed convergence check
     double est_check;   // predicted relative residual that triggered the pending check
     double Q_in, Q_out, xr;  // fluxes and x.(b - A x) from the last refresh
-    uint32_t pad1_, pad2_;
+    // to 256 bytes: control blocks of different networks share no 128-byte
+    // line, so networks placed on different XCDs never write one line
+    uint32_t pad_[10];
 };
 
 constexpr int kRed = 5;          // partial sums per workgroup
@@ -125,7 +127,7 @@ template <typename T>
 hipError_t launch_scale(const Lat &L, const double *const g[3], const uint8_t *mask, T *const gT[3], T *vec,
                         int64_t nvec, hipStream_t st);
 hipError_t launch_direct_flux(const Lat &L, const double *ga, double *out, hipStream_t st);
-// zero n <= 64 counters with a kernel (no memset node, so a captured graph may hold it)
+// zero n counters with a kernel (no memset node, so a captured graph may hold it)
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st);
 // g[i] in [1, 2) from a hash of i and salt (the networks of the launch-shape trials)
 hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st);
@@ -151,13 +153,18 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
                        int slot, hipStream_t st);
 // `rounds` pass rounds of every network in the block table in one launch
 // (rounds round_base .. round_base + rounds - 1 of the engine); dim, tab,
-// blk, scal, nblocks and slot as for launch_pass. *err (device memory, zero on
-// entry) becomes nonzero when a wait exceeded its bound; *queue (device
-// memory, one 8-byte word the launcher clears) is the launch's item counter.
+// blk, scal and slot as for launch_pass, nblocks the table's length. coh 1:
+// items in one queue (xoff = {0, nblocks, ..., nblocks}), any workgroup takes
+// any item, the state moves by device-scope accesses; coh 2: entries
+// xoff[x] .. xoff[x + 1] - 1 (9 ints, device memory) are the networks the
+// host placed on XCD x, claimed only by workgroups running there. *err
+// (device memory, zero on entry) becomes nonzero when a wait exceeded its
+// bound; queues (device memory, 8 x 32 words, cleared by the launcher) are
+// the per-XCD item counters.
 template <typename T>
-hipError_t launch_pass_persist(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks,
-                               int64_t round_base, int rounds, int slot, unsigned *err, unsigned long long *queue,
-                               hipStream_t st);
+hipError_t launch_pass_persist(int dim, int coh, const PassArgs<T> *tab, const uint2 *blk, const int *xoff,
+                               Scalars *scal, int nblocks, int64_t round_base, int rounds, int slot, unsigned *err,
+                               unsigned long long *queues, hipStream_t st);
 
 // tile geometry of the pass kernels: a 2D workgroup tile is 64 kSEG2f x
 // 4 kTY2f (FP32) or 64 kSEG2d x 4 kTY2d (FP64): each wave holds kTY2f / kTY2d

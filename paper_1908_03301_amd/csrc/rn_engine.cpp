@@ -419,13 +419,17 @@ int Engine::init(hipStream_t st, std::string *err)
     // of a small pass is spent on the device, not in the launch call.
     const char *g = std::getenv("RN_GRAPHS");
     use_graph_ = g && g[0] == '1';
-    // persistent launches are opt-in (RN_PERSIST=1): measured slower than one
-    // launch per round on every workload here (their device-scope state
-    // accesses give up the L2), though bit-identical to it
+    // persistent launches are opt-in, bit-identical to one launch per round:
+    // RN_PERSIST=1 (items on all XCDs) measured slower on every workload here,
+    // RN_PERSIST=2 (each small network on one XCD) 2% faster on a 128^2
+    // solve and even on batches, whose time is in the large networks
     const char *pe = std::getenv("RN_PERSIST");
-    persist_ = pe && pe[0] == '1';
+    persist_mode_ = (pe && pe[0] == '1') ? 1 : ((pe && pe[0] == '2') ? 2 : 0);
+    persist_ = persist_mode_ != 0;
     if (persist_) use_graph_ = false;
-    ENG_TRY(hipMalloc(&d_queue_, 256 * kKinds));
+    ENG_TRY(hipMalloc(&d_queue_, kQueueWords * sizeof(unsigned long long) * kKinds));
+    ENG_TRY(hipMalloc(&d_xoff_, sizeof(int) * 16 * kKinds));
+    ENG_TRY(hipHostMalloc((void **)&h_xoff_, sizeof(int) * 16 * kKinds * 2, hipHostMallocDefault));
     ENG_TRY(hipMalloc(&d_err_, 256));
     ENG_TRY(hipMemset(d_err_, 0, 256));
     ENG_TRY(hipHostMalloc((void **)&h_err_, 256, hipHostMallocDefault));
@@ -459,6 +463,10 @@ void Engine::destroy()
     (void)hipFree(d_err_);
     (void)hipFree(d_queue_);
     d_queue_ = nullptr;
+    (void)hipFree(d_xoff_);
+    (void)hipHostFree(h_xoff_);
+    d_xoff_ = nullptr;
+    h_xoff_ = nullptr;
     (void)hipHostFree(h_err_);
     d_err_ = h_err_ = nullptr;
     for (int k = 0; k < kKinds; ++k) {
@@ -685,12 +693,51 @@ int Engine::rebuild(hipStream_t st, std::string *err)
                 single_[k] = n->slot;
             }
         if (nets != 1) single_[k] = -1;
-        uint2 *h = h_blk_[k] + (size_t)half_ * blk_cap_[k];
-        int m = 0;
+        // how this kind's chunk runs: one launch per round (coherence 0), a
+        // persistent launch over all XCDs (1), or a persistent launch with
+        // each network on one XCD (2, when every network of the kind is small
+        // enough that one XCD's workgroups hold a pass of it)
+        int grid_max = 0;
         for (Net *n : active_)
-            if (n->kind == k)
-                for (int b = 0; b < n->L.grid; ++b) h[m++] = make_uint2((unsigned)n->slot, (unsigned)b);
+            if (n->kind == k) grid_max = std::max(grid_max, n->L.grid);
+        kind_coh_[k] = persist_mode_ == 1 ? 1 : ((persist_mode_ == 2 && grid_max <= kXcdMaxGrid) ? 2 : 0);
+        uint2 *h = h_blk_[k] + (size_t)half_ * blk_cap_[k];
+        int *xo = h_xoff_ + (size_t)(half_ * kKinds + k) * 16;
+        int m = 0;
+        if (kind_coh_[k] == 2) {
+            // place the networks on the 8 XCDs, largest first, each on the XCD
+            // with the fewest workgroups so far; the table lists XCD 0's
+            // networks, then XCD 1's, and so on
+            std::vector<Net *> nk;
+            for (Net *n : active_)
+                if (n->kind == k) nk.push_back(n);
+            std::stable_sort(nk.begin(), nk.end(), [](const Net *a, const Net *b) { return a->L.grid > b->L.grid; });
+            int64_t load[8] = {};
+            std::vector<int> place(nk.size());
+            for (size_t i = 0; i < nk.size(); ++i) {
+                int best = 0;
+                for (int x = 1; x < 8; ++x)
+                    if (load[x] < load[best]) best = x;
+                place[i] = best;
+                load[best] += nk[i]->L.grid;
+            }
+            for (int x = 0; x < 8; ++x) {
+                xo[x] = m;
+                for (size_t i = 0; i < nk.size(); ++i)
+                    if (place[i] == x)
+                        for (int b = 0; b < nk[i]->L.grid; ++b) h[m++] = make_uint2((unsigned)nk[i]->slot, (unsigned)b);
+            }
+            xo[8] = m;
+            single_[k] = -1;
+        } else {
+            for (Net *n : active_)
+                if (n->kind == k)
+                    for (int b = 0; b < n->L.grid; ++b) h[m++] = make_uint2((unsigned)n->slot, (unsigned)b);
+            xo[0] = 0;
+            for (int x = 1; x <= 8; ++x) xo[x] = m;
+        }
         ENG_TRY(hipMemcpyAsync(d_blk_[k], h, sizeof(uint2) * m, hipMemcpyHostToDevice, st));
+        ENG_TRY(hipMemcpyAsync(d_xoff_ + 16 * k, xo, sizeof(int) * 9, hipMemcpyHostToDevice, st));
     }
     dirty_ = false;
     return RN_OK;
@@ -733,7 +780,7 @@ int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
     for (int i = 0; i < rounds; ++i) {
         const int par = (int)((rounds_ + i) & 1);
         for (int k = 0; k < kKinds; ++k) {
-            if (!nblk_[k]) continue;
+            if (!nblk_[k] || kind_coh_[k] != 0) continue;
             const int dim = kind_dim(k);
             const uint2 *blk = single_[k] >= 0 ? nullptr : d_blk_[k];
             if (!kind_fp64(k))
@@ -749,25 +796,28 @@ int Engine::launch_rounds(int rounds, hipStream_t st, std::string *err)
     return RN_OK;
 }
 
-// One persistent launch per kind runs all `rounds` rounds of its networks.
+// One persistent launch per kind whose coherence mode is 1 or 2 runs all
+// `rounds` rounds of its networks; the other kinds get one launch per round.
 int Engine::launch_persistent(int rounds, hipStream_t st, std::string *err)
 {
     for (int k = 0; k < kKinds; ++k) {
-        if (!nblk_[k]) continue;
+        if (!nblk_[k] || kind_coh_[k] == 0) continue;
         const int dim = kind_dim(k);
         const uint2 *blk = single_[k] >= 0 ? nullptr : d_blk_[k];
+        unsigned long long *q = d_queue_ + (size_t)kQueueWords * k;
+        const int *xo = d_xoff_ + 16 * k;
         if (!kind_fp64(k))
-            ENG_TRY(launch_pass_persist<float>(dim, d_tabf_, blk, d_scal_, nblk_[k], rounds_, rounds, single_[k],
-                                               d_err_, d_queue_ + 32 * k, st));
+            ENG_TRY(launch_pass_persist<float>(dim, kind_coh_[k], d_tabf_, blk, xo, d_scal_, nblk_[k], rounds_, rounds,
+                                               single_[k], d_err_, q, st));
         else
-            ENG_TRY(launch_pass_persist<double>(dim, d_tabd_, blk, d_scal_, nblk_[k], rounds_, rounds, single_[k],
-                                                d_err_, d_queue_ + 32 * k, st));
+            ENG_TRY(launch_pass_persist<double>(dim, kind_coh_[k], d_tabd_, blk, xo, d_scal_, nblk_[k], rounds_,
+                                                rounds, single_[k], d_err_, q, st));
         if (recording_) {
             int r = record_timing(k, st, err);
             if (r) return r;
         }
     }
-    return RN_OK;
+    return launch_rounds(rounds, st, err);
 }
 
 int Engine::capture(hipStream_t st, std::string *err)
@@ -834,7 +884,8 @@ int Engine::launch_chunk(int rounds, hipStream_t st, std::string *err)
         if (r) return r;
     }
     rounds_ += rounds;
-    launches_ += persist_ ? (int64_t)kinds : (int64_t)rounds * kinds;
+    for (int k = 0; k < kKinds; ++k)
+        if (nblk_[k]) launches_ += (persist_ && kind_coh_[k] != 0) ? 1 : rounds;
     int hi = 0;
     for (Net *n : active_) hi = std::max(hi, n->slot + 1);
     const int b = next_mirror_;

@@ -66,28 +66,42 @@ __device__ __forceinline__ void st_through(double *p, double v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Loads and stores of the CG state. Between launches (COH = false) plain
-// accesses suffice: a kernel boundary makes every store visible. Inside a
-// persistent launch (COH = true) a pass reads what other workgroups, on other
-// XCDs with their own L2s, wrote in the previous pass, and its own XCD's L2
-// may still hold the buffer from two passes back: the state then moves by
-// device-scope accesses (global_load / global_store with sc1), which write
-// through the L2 and do not return a line another XCD has since written.
+// Loads and stores of the CG state, by coherence mode:
+//   COH 0 (one launch per round): plain accesses; a kernel boundary makes
+//     every store visible to the next launch, on any XCD.
+//   COH 1 (persistent launch, a network's items on any XCD): a pass reads
+//     what workgroups on other XCDs, with their own L2s, wrote in the previous
+//     pass, and its own XCD's L2 may still hold the buffer from two passes
+//     back, so the state moves by device-scope accesses (global_load /
+//     global_store with sc1), which write through the L2 and do not return a
+//     line another XCD has since written.
+//   COH 2 (persistent launch, all items of a network on one XCD): the state
+//     is coherent in that XCD's L2, so stores are plain (the per-CU L1 writes
+//     through to it). Loads are still device-scope (sc1): a workgroup-scope
+//     load (sc0) or a plain one is served by the CU's own L1, which keeps a
+//     line another CU has since written (outside threadgroup-split mode the
+//     memory model lets workgroup scope hit L1); sc1 loads skip L1 and hit L2.
 // The bonds, the mask and the FP64 conductances are read-only during the
-// iterations and keep plain loads.
-template <bool COH, typename T>
+// iterations and keep plain loads in every mode.
+template <int COH, typename T>
 __device__ __forceinline__ T ldc(const T *p)
 {
-    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (COH != 0) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else return *p;
 }
 
-template <bool COH, typename T>
+template <int COH, typename T>
 __device__ __forceinline__ void stc(T *p, T v)
 {
-    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (COH == 1) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
 }
+
+// The memory scope of the reduction's own stores (partials, ticket resets,
+// control block) in each mode: across XCDs unless the network is on one.
+// Its loads are device-scope in every persistent mode (see ldc).
+template <int COH>
+constexpr int store_scope() { return COH == 2 ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT; }
 
 // Workgroup index -> tile index so that each XCD (workgroups are dealt to the
 // 8 XCDs round-robin) owns one contiguous range of tiles and shares halos in
@@ -251,7 +265,7 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
 // register, so the last workgroup's scalar step runs on an LDS copy instead of
 // waiting for a chain of memory round trips after the reduction.
 constexpr int kScalWords = (int)(sizeof(Scalars) / 8);
-static_assert(sizeof(Scalars) % 8 == 0 && kScalWords <= kBlock, "control block words");
+static_assert(sizeof(Scalars) == 256 && kScalWords <= kBlock, "control block words: one 256-byte block per network");
 constexpr int kModeWord = (int)(offsetof(Scalars, mode) / 8);
 static_assert(offsetof(Scalars, mode) == 0, "mode is the low half of the first control block word");
 constexpr int kPassesWord = (int)(offsetof(Scalars, passes) / 8);
@@ -271,11 +285,12 @@ __device__ __forceinline__ unsigned long long prefetch_scalars(const Scalars *s)
 // on the top counter. Device-scope atomics on one address are serviced one
 // after another, so a single counter for a 2048-workgroup pass queued 2048
 // atomics at the end of every pass.
-// COH (persistent launches): every wave first waits for its own state stores
-// to complete, so that a workgroup counts only once its tile is in memory, and
-// the last workgroup publishes the control block with device-scope stores,
-// the pass count last (the word later passes of the same network wait on).
-template <bool COH>
+// COH 1, 2 (persistent launches): every wave first waits for its own state
+// stores to complete, so that a workgroup counts only once its tile is
+// visible, and the last workgroup publishes the control block, the pass count
+// last (the word later passes of the same network wait on). With COH 2 the
+// partials, tickets and control block stay in the network's XCD's L2.
+template <int COH>
 __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tickets, Scalars *s, int lb, int grid,
                             int groups, int mode, unsigned long long spre)
 {
@@ -284,7 +299,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     __shared__ unsigned long long sl[kScalWords];
     constexpr int kStride = kTicketStride / (int)sizeof(unsigned);
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    if constexpr (COH) __builtin_amdgcn_s_waitcnt(0);
+    if constexpr (COH != 0) __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
     for (int k = 0; k < kRed; ++k) {
         double v = wave_sum(acc[k]);
@@ -295,7 +310,8 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
         for (int k = 0; k < kRed; ++k) {
             double v = 0.0;
             for (int ww = 0; ww < kBlock / kWave; ++ww) v += red[ww][k];
-            st_through(&partials[(size_t)lb * kRed + k], v);
+            if constexpr (COH == 2) partials[(size_t)lb * kRed + k] = v;
+            else st_through(&partials[(size_t)lb * kRed + k], v);
         }
         // wait until this thread's write-through stores have completed
         // (s_waitcnt with every counter at 0), then count (device-scope
@@ -318,7 +334,10 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     for (int k = 0; k < kRed; ++k) tot[k] = 0.0;
     for (int b = threadIdx.x; b < grid; b += kBlock)
 #pragma unroll
-        for (int k = 0; k < kRed; ++k) tot[k] += ld_through(&partials[(size_t)b * kRed + k]);
+        for (int k = 0; k < kRed; ++k)
+            tot[k] += COH == 2 ? __hip_atomic_load(&partials[(size_t)b * kRed + k], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : ld_through(&partials[(size_t)b * kRed + k]);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kRed; ++k) {
@@ -327,7 +346,7 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     }
     // every workgroup has counted: clear the counters for the next pass
     if (threadIdx.x <= groups)
-        __hip_atomic_store(tickets + threadIdx.x * kStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(tickets + threadIdx.x * kStride, 0u, __ATOMIC_RELAXED, store_scope<COH>());
     if (threadIdx.x < kScalWords) sl[threadIdx.x] = spre;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -342,13 +361,12 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
     }
     __syncthreads();
     unsigned long long *sw = reinterpret_cast<unsigned long long *>(s);
-    if constexpr (COH) {
+    if constexpr (COH != 0) {
         const int t = (int)threadIdx.x;
-        if (t < kScalWords && t != kPassesWord)
-            __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t < kScalWords && t != kPassesWord) __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, store_scope<COH>());
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (t == kPassesWord) __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == kPassesWord) __hip_atomic_store(sw + t, sl[t], __ATOMIC_RELAXED, store_scope<COH>());
     } else {
         if (threadIdx.x < kScalWords) sw[threadIdx.x] = sl[threadIdx.x];
     }
@@ -399,7 +417,7 @@ __device__ __forceinline__ double with_steps(double P, double sa2, double p2, do
 // issued before any branch on its data: two memory round trips per node, and
 // few enough registers that the rare refresh does not lower the occupancy of
 // the CG pass that shares its kernel.
-template <typename T, int DIM, bool COH>
+template <typename T, int DIM, int COH>
 __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double *__restrict__ Ps,
                                              double *__restrict__ Pd, int x, int y, int z, const Step<T> &k_,
                                              double sigma_next, bool bonly, double (&acc)[kRed])
@@ -515,7 +533,7 @@ struct Tile2D {
     static constexpr int COLS = kWave * SEG;                                          // columns per workgroup
 };
 
-template <typename T, int SHAPE, bool COH>
+template <typename T, int SHAPE, int COH>
 __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int yb, int lane,
                                           int w, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
@@ -771,11 +789,11 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
                 const int x = x0 + kWave * sg + lane;
                 if (x < a.nx)
                     for (int yy = y0; yy < y1; ++yy)
-                        refresh_node<T, 2, false>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
+                        refresh_node<T, 2, 0>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
             }
         }
         // (a rare pass: the control block is read here, not held through the refresh)
-        finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, prefetch_scalars(s));
+        finish_pass<0>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, prefetch_scalars(s));
         return;
     }
     const unsigned long long spre = prefetch_scalars(s);
@@ -787,9 +805,9 @@ __global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__res
         const int tx = tile % a.ntx, ty = tile / a.ntx;
         const int x0 = tx * Tile2D<T, SHAPE>::COLS;
         const int yb = ty * Tile2D<T, SHAPE>::ROWS;
-        cg2d_tile<T, SHAPE, false>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
+        cg2d_tile<T, SHAPE, 0>(a, a.P[m], x0, yb, lane, w, (T)s->alpha, (T)s->beta, st, acc);
     }
-    finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    finish_pass<0>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
 }
 
 // ---------------------------------------------------------------- 3D pass
@@ -820,7 +838,7 @@ struct Bond3 {                 // bonds of one plane for this thread's rows
     T yh;                      // bond from the row above this wave's first row
 };
 
-template <typename T, bool COH>
+template <typename T, int COH>
 __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restrict__ P, int x0, int y0, int z0,
                                           int z1, T alpha, T beta, const Step<T> &k, double (&acc)[kRed])
 {
@@ -1056,7 +1074,7 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
         const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
         const int z1 = min(z0 + a.tile_z, a.nz);
         if (mode == MODE_CG) {
-            cg3d_tile<T, false>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, st, acc);
+            cg3d_tile<T, 0>(a, a.P[m], x0, y0, z0, z1, (T)s->alpha, (T)s->beta, st, acc);
         } else {
             const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
             const double sigma_next = s->sigma_next;
@@ -1067,11 +1085,11 @@ __global__ __launch_bounds__(kBlock) void pass3d_kernel(const PassArgs<T> *__res
                     const int yy = y0 + w * kRows + j;
                     if (yy >= a.ny) break;
                     for (int zz = z0; zz < z1; ++zz)
-                        refresh_node<T, 3, false>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
+                        refresh_node<T, 3, 0>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
                 }
         }
     }
-    finish_pass<false>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+    finish_pass<0>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
 }
 
 // ---------------------------------------------------------------- persistent pass kernels
@@ -1098,14 +1116,14 @@ constexpr uint64_t kSpinTicks = 200000000ull;   // 2 s of the 100 MHz s_memrealt
 // err[0] = 1 once a wait gave up; the first to give up records what it saw
 // in err[1..6]: network slot, passes needed, passes seen, mode seen, round
 // and table entry of its item.
+template <int COH>
 __device__ __forceinline__ int await_pass(const Scalars *s, int64_t need, unsigned *err, unsigned slot,
                                           int round, int entry)
 {
     const unsigned long long *w = reinterpret_cast<const unsigned long long *>(s);
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
     while (true) {
-        const unsigned long long done = __hip_atomic_load(w + kPassesWord, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long done = __hip_atomic_load(w + kPassesWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long mw = __hip_atomic_load(w + kModeWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((int)(uint32_t)mw == MODE_DONE) return 1;   // finished: the item is skipped
         if ((int64_t)done >= need) return 1;
@@ -1128,11 +1146,12 @@ __device__ __forceinline__ int await_pass(const Scalars *s, int64_t need, unsign
 // Wait for the item's network, then load its control block into LDS (one
 // 8-byte word per thread, device-scope loads). Returns the word this thread
 // holds (for finish_pass) and whether the item runs.
+template <int COH>
 __device__ __forceinline__ bool begin_item(Scalars *s, int64_t need, unsigned *err, int it_parity,
                                            unsigned long long (&snap)[kScalWords], int (&go)[2],
                                            unsigned long long &spre, unsigned slot, int round, int entry)
 {
-    if (threadIdx.x == 0) go[it_parity] = await_pass(s, need, err, slot, round, entry);
+    if (threadIdx.x == 0) go[it_parity] = await_pass<COH>(s, need, err, slot, round, entry);
     __syncthreads();
     if (!go[it_parity]) return false;
     const unsigned long long *w = reinterpret_cast<const unsigned long long *>(s);
@@ -1192,29 +1211,43 @@ __device__ __forceinline__ int64_t next_claim(unsigned long long (&claim)[2], in
     return v;
 }
 
-template <typename T, int SHAPE>
+// The XCD a workgroup runs on (the XCC_ID hardware register), for COH 2,
+// where a network's items are claimed only by workgroups of the XCD the host
+// placed it on.
+__device__ __forceinline__ int my_xcd()
+{
+    return __builtin_amdgcn_readfirstlane(__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20)) & 7;
+}
+
+// Items of the launch: table entries xoff[x] .. xoff[x + 1] - 1 belong to
+// queue x (x = the workgroup's XCD with COH 2, else 0), and item it of queue x
+// is round it / n_x of entry xoff[x] + it % n_x.
+template <typename T, int SHAPE, int COH>
 __global__ __launch_bounds__(kBlock) void pass2d_persist(const PassArgs<T> *__restrict__ tab,
-                                                         const uint2 *__restrict__ blk, Scalars *scal, int nblk,
-                                                         int64_t round_base, int rounds, int slot, unsigned *err,
-                                                         unsigned long long *queue)
+                                                         const uint2 *__restrict__ blk, const int *__restrict__ xoff,
+                                                         Scalars *scal, int64_t round_base, int rounds, int slot,
+                                                         unsigned *err, unsigned long long *queues)
 {
     __shared__ unsigned long long snap[kScalWords];
     __shared__ int go[2];
     __shared__ unsigned long long claim[2];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int x = COH == 2 ? my_xcd() : 0;
+    const int base = xoff[x], nblk = xoff[x + 1] - base;
+    unsigned long long *queue = queues + 32 * x;
     const int64_t total = (int64_t)rounds * nblk;
     int itp = 0;
     for (int64_t it = first_claim(queue, claim); it < total; it = next_claim(claim, itp), itp ^= 1) {
         if (threadIdx.x == 0) claim[itp ^ 1] = __hip_atomic_fetch_add(queue, 1ull, __ATOMIC_RELAXED,
                                                                         __HIP_MEMORY_SCOPE_AGENT);
         const int r = (int)(it / nblk);
-        const int j = (int)(it - (int64_t)r * nblk);
+        const int j = base + (int)(it - (int64_t)r * nblk);
         const uint2 e = blk ? blk[j] : make_uint2((unsigned)slot, (unsigned)j);
         const int parity = (int)((round_base + r) & 1);
         const PassArgs<T> &a = tab[2 * e.x + parity];
         Scalars *s = scal + e.x;
         unsigned long long spre = 0;
-        if (!begin_item(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
+        if (!begin_item<COH>(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
         const Scalars u = uniform_scalars(reinterpret_cast<const Scalars *>(snap));
         const Scalars *sv = &u;
         const int mode = sv->mode;
@@ -1234,10 +1267,10 @@ __global__ __launch_bounds__(kBlock) void pass2d_persist(const PassArgs<T> *__re
                 const int y0 = ty * Tile2D<T, SHAPE>::ROWS + w * Tile2D<T, SHAPE>::TY;
                 const int y1 = min(y0 + Tile2D<T, SHAPE>::TY, a.ny);
                 for (int sg = 0; sg < Tile2D<T, SHAPE>::SEG; ++sg) {
-                    const int x = x0 + kWave * sg + lane;
-                    if (x < a.nx)
+                    const int xx = x0 + kWave * sg + lane;
+                    if (xx < a.nx)
                         for (int yy = y0; yy < y1; ++yy)
-                            refresh_node<T, 2, true>(a, a.P[m], a.P[m ^ 1], x, yy, 0, st, sigma_next, bonly, acc);
+                            refresh_node<T, 2, COH>(a, a.P[m], a.P[m ^ 1], xx, yy, 0, st, sigma_next, bonly, acc);
                 }
             }
         } else {
@@ -1247,36 +1280,38 @@ __global__ __launch_bounds__(kBlock) void pass2d_persist(const PassArgs<T> *__re
                 if (tile >= a.ntiles) break;
                 if (k > 0) __syncthreads();          // the previous tile's LDS rows are reused
                 const int tx = tile % a.ntx, ty = tile / a.ntx;
-                cg2d_tile<T, SHAPE, true>(a, a.P[m], tx * Tile2D<T, SHAPE>::COLS, ty * Tile2D<T, SHAPE>::ROWS, lane,
-                                          w, alpha, beta, st, acc);
+                cg2d_tile<T, SHAPE, COH>(a, a.P[m], tx * Tile2D<T, SHAPE>::COLS, ty * Tile2D<T, SHAPE>::ROWS, lane,
+                                         w, alpha, beta, st, acc);
             }
         }
-        finish_pass<true>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+        finish_pass<COH>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void pass3d_persist(const PassArgs<T> *__restrict__ tab,
-                                                         const uint2 *__restrict__ blk, Scalars *scal, int nblk,
-                                                         int64_t round_base, int rounds, int slot, unsigned *err,
-                                                         unsigned long long *queue)
+template <typename T, int COH>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void pass3d_persist(
+    const PassArgs<T> *__restrict__ tab, const uint2 *__restrict__ blk, const int *__restrict__ xoff, Scalars *scal,
+    int64_t round_base, int rounds, int slot, unsigned *err, unsigned long long *queues)
 {
     __shared__ unsigned long long snap[kScalWords];
     __shared__ int go[2];
     __shared__ unsigned long long claim[2];
+    const int x = COH == 2 ? my_xcd() : 0;
+    const int base = xoff[x], nblk = xoff[x + 1] - base;
+    unsigned long long *queue = queues + 32 * x;
     const int64_t total = (int64_t)rounds * nblk;
     int itp = 0;
     for (int64_t it = first_claim(queue, claim); it < total; it = next_claim(claim, itp), itp ^= 1) {
         if (threadIdx.x == 0) claim[itp ^ 1] = __hip_atomic_fetch_add(queue, 1ull, __ATOMIC_RELAXED,
                                                                         __HIP_MEMORY_SCOPE_AGENT);
         const int r = (int)(it / nblk);
-        const int j = (int)(it - (int64_t)r * nblk);
+        const int j = base + (int)(it - (int64_t)r * nblk);
         const uint2 e = blk ? blk[j] : make_uint2((unsigned)slot, (unsigned)j);
         const int parity = (int)((round_base + r) & 1);
         const PassArgs<T> &a = tab[2 * e.x + parity];
         Scalars *s = scal + e.x;
         unsigned long long spre = 0;
-        if (!begin_item(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
+        if (!begin_item<COH>(s, round_base + r - a.round0, err, itp, snap, go, spre, e.x, r, j)) continue;
         const Scalars u = uniform_scalars(reinterpret_cast<const Scalars *>(snap));
         const Scalars *sv = &u;
         const int mode = sv->mode;
@@ -1292,25 +1327,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
             const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * a.tile_z;
             const int z1 = min(z0 + a.tile_z, a.nz);
             if (mode == MODE_CG) {
-                cg3d_tile<T, true>(a, a.P[m], x0, y0, z0, z1, (T)sv->alpha, (T)sv->beta, st, acc);
+                cg3d_tile<T, COH>(a, a.P[m], x0, y0, z0, z1, (T)sv->alpha, (T)sv->beta, st, acc);
             } else {
                 const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
                 const double sigma_next = sv->sigma_next;
                 const bool bonly = sv->first == 1;
-                const int x = x0 + lane;
-                if (x < a.nx)
+                const int xx = x0 + lane;
+                if (xx < a.nx)
                     for (int jj = 0; jj < kRows; ++jj) {
                         const int yy = y0 + w * kRows + jj;
                         if (yy >= a.ny) break;
                         for (int zz = z0; zz < z1; ++zz)
-                            refresh_node<T, 3, true>(a, a.P[m], a.P[m ^ 1], x, yy, zz, st, sigma_next, bonly, acc);
+                            refresh_node<T, 3, COH>(a, a.P[m], a.P[m ^ 1], xx, yy, zz, st, sigma_next, bonly, acc);
                     }
             }
-        } else {
-            // an idle workgroup of the padded grid still reaches the reduction;
-            // the 3D tile's LDS is reused by the next item after its barriers
         }
-        finish_pass<true>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
+        // an idle workgroup of the padded grid still reaches the reduction
+        finish_pass<COH>(acc, a.partials, a.tickets, s, lb, a.grid, a.groups, mode, spre);
     }
 }
 
@@ -1537,7 +1570,7 @@ __global__ void direct_flux_kernel(Lat L, const double *ga, double *out)
 
 __global__ void clear_u64_kernel(unsigned long long *p, int n)
 {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) p[i] = 0ull;
 }
 
 // Conductances of the launch-shape trials: values in [1, 2) from a
@@ -1660,7 +1693,7 @@ hipError_t launch_pass(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalar
 
 // Workgroups of one persistent launch: as many as the kernel's occupancy
 // keeps resident on all CUs at once (more would only queue behind them).
-template <typename T>
+template <typename T, int COH>
 static hipError_t persist_capacity(int dim, int *cap)
 {
     static int cached[2][3] = {{0, 0, 0}, {0, 0, 0}};
@@ -1673,9 +1706,9 @@ static hipError_t persist_capacity(int dim, int *cap)
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    if (dim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 0>, kBlock, 0);
-    else if (dim == -2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 1>, kBlock, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass3d_persist<T>, kBlock, 0);
+    if (dim == 2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 0, COH>, kBlock, 0);
+    else if (dim == -2) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass2d_persist<T, 1, COH>, kBlock, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pass3d_persist<T, COH>, kBlock, 0);
     if (e != hipSuccess) return e;
     if (per < 1 || cus < 1) return hipErrorInvalidConfiguration;
     cached[fi][di] = per * cus;
@@ -1683,33 +1716,46 @@ static hipError_t persist_capacity(int dim, int *cap)
     return hipSuccess;
 }
 
-template <typename T>
-hipError_t launch_pass_persist(int dim, const PassArgs<T> *tab, const uint2 *blk, Scalars *scal, int nblocks,
-                               int64_t round_base, int rounds, int slot, unsigned *err, unsigned long long *queue,
-                               hipStream_t st)
+template <typename T, int COH>
+static hipError_t persist_launch(int dim, const PassArgs<T> *tab, const uint2 *blk, const int *xoff, Scalars *scal,
+                                 int nblocks, int64_t round_base, int rounds, int slot, unsigned *err,
+                                 unsigned long long *queues, hipStream_t st)
 {
-    if (nblocks <= 0 || rounds <= 0) return hipSuccess;
     int cap = 0;
-    hipError_t e = persist_capacity<T>(dim, &cap);
+    hipError_t e = persist_capacity<T, COH>(dim, &cap);
     if (e != hipSuccess) return e;
+    // every XCD needs workgroups of its own for COH 2 (workgroups are dealt to
+    // the 8 XCDs in turn, so any grid of at least 8 covers them)
     const int64_t items = (int64_t)nblocks * rounds;
-    const int grid = (int)std::min<int64_t>(items, (int64_t)cap);
-    // the queue counter starts at 0 (a kernel, not a memset node)
-    e = launch_clear_u64(queue, 1, st);
+    const int grid = (int)std::max<int64_t>(COH == 2 ? 64 : 1, std::min<int64_t>(items, (int64_t)cap));
+    // the queue counters start at 0 (a kernel, not a memset node)
+    e = launch_clear_u64(queues, 32 * 8, st);
     if (e != hipSuccess) return e;
     if (dim == 2)
-        pass2d_persist<T, 0><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+        pass2d_persist<T, 0, COH><<<grid, kBlock, 0, st>>>(tab, blk, xoff, scal, round_base, rounds, slot, err, queues);
     else if (dim == -2)
-        pass2d_persist<T, 1><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+        pass2d_persist<T, 1, COH><<<grid, kBlock, 0, st>>>(tab, blk, xoff, scal, round_base, rounds, slot, err, queues);
     else
-        pass3d_persist<T><<<grid, kBlock, 0, st>>>(tab, blk, scal, nblocks, round_base, rounds, slot, err, queue);
+        pass3d_persist<T, COH><<<grid, kBlock, 0, st>>>(tab, blk, xoff, scal, round_base, rounds, slot, err, queues);
     return hipGetLastError();
 }
 
-template hipError_t launch_pass_persist<float>(int, const PassArgs<float> *, const uint2 *, Scalars *, int, int64_t,
-                                               int, int, unsigned *, unsigned long long *, hipStream_t);
-template hipError_t launch_pass_persist<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int64_t,
-                                                int, int, unsigned *, unsigned long long *, hipStream_t);
+template <typename T>
+hipError_t launch_pass_persist(int dim, int coh, const PassArgs<T> *tab, const uint2 *blk, const int *xoff,
+                               Scalars *scal, int nblocks, int64_t round_base, int rounds, int slot, unsigned *err,
+                               unsigned long long *queues, hipStream_t st)
+{
+    if (nblocks <= 0 || rounds <= 0) return hipSuccess;
+    if (coh == 2) return persist_launch<T, 2>(dim, tab, blk, xoff, scal, nblocks, round_base, rounds, slot, err, queues, st);
+    return persist_launch<T, 1>(dim, tab, blk, xoff, scal, nblocks, round_base, rounds, slot, err, queues, st);
+}
+
+template hipError_t launch_pass_persist<float>(int, int, const PassArgs<float> *, const uint2 *, const int *,
+                                               Scalars *, int, int64_t, int, int, unsigned *, unsigned long long *,
+                                               hipStream_t);
+template hipError_t launch_pass_persist<double>(int, int, const PassArgs<double> *, const uint2 *, const int *,
+                                                Scalars *, int, int64_t, int, int, unsigned *, unsigned long long *,
+                                                hipStream_t);
 template hipError_t launch_scale<float>(const Lat &, const double *const[3], const uint8_t *, float *const[3],
                                         float *, int64_t, hipStream_t);
 template hipError_t launch_scale<double>(const Lat &, const double *const[3], const uint8_t *, double *const[3],

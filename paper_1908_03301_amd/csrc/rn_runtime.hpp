@@ -201,12 +201,16 @@ private:
     int launch_rounds(int rounds, hipStream_t st, std::string *err);
     int launch_persistent(int rounds, hipStream_t st, std::string *err);
     int capture(hipStream_t st, std::string *err);
-    // persistent launches: `rounds` pass rounds of a kind in one launch
-    // (RN_PERSIST=0 falls back to one launch per round and kind)
-    bool persist_ = true;
+    // persistent launches (RN_PERSIST=1 or 2): `rounds` pass rounds of a kind in one launch
+    bool persist_ = false;
+    int persist_mode_ = 0;                   // RN_PERSIST: 0 off, 1 persistent over all XCDs, 2 one XCD per network
+    int kind_coh_[kKinds] = {};              // per kind, this chunk: 0 one launch per round, 1 or 2 persistent
+    static constexpr int kXcdMaxGrid = 256;  // largest network (workgroups per pass) placed on one XCD
+    static constexpr int kQueueWords = 8 * 32;   // per kind: 8 item counters, 256 bytes apart
+    int *d_xoff_ = nullptr, *h_xoff_ = nullptr;  // per kind, 9 table offsets (16 ints), host staging x2
     hipStream_t side_ = nullptr;
     unsigned *d_err_ = nullptr, *h_err_ = nullptr;   // a bounded wait gave up (device word, pinned mirror)
-    unsigned long long *d_queue_ = nullptr;          // item counters of the persistent launches, 256 B per kind
+    unsigned long long *d_queue_ = nullptr;          // item counters of the persistent launches, kQueueWords per kind
     // timing: events of the chunk behind mirror b, tev_[b][0] before its first
     // launch and tev_[b][i + 1] after launch i, whose kind is tkind_[b][i]
     bool timing_ = false, recording_ = false;

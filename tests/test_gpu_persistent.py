@@ -1,15 +1,18 @@
 """GPU tests of the persistent pass kernels against the one-round-per-launch kernels.
 
-By default a context runs one pass kernel launch per round and kind; a
+By default a context runs one pass kernel launch per round and kind. A
 context created with RN_PERSIST=1 in the environment runs every chunk of
-rounds of a kind in one persistent launch, where a network's passes read each other's state
-through device-scope loads and stores and wait on the network's published
-pass count. Both run the same tile code and the same fixed-order reduction,
-so every result field and every pressure must be bit-identical: alone, in a
-batch of uneven networks (2D full / small tiles, two tiles per workgroup,
-3D tiles of several depths, both precisions, both side conditions, a
-network with no live node) and in the served stream. The mixed results are
-also held to the oracle's K (Sec. II, Eqs. 3-4).
+rounds of a kind in one persistent launch, where a network's passes read
+each other's state through device-scope loads and stores and wait on the
+network's published pass count; with RN_PERSIST=2 every network small enough
+is placed on one XCD and its items are claimed only by workgroups there (the
+XCC_ID register), so its state stays coherent in that XCD's L2 (larger
+networks keep one launch per round). All run the same tile code and the same
+fixed-order reduction, so every result field and every pressure must be
+bit-identical: alone, in a batch of uneven networks (2D full / small tiles,
+two tiles per workgroup, 3D tiles of several depths, both precisions, both
+side conditions, a network with no live node) and in the served stream. The
+mixed results are also held to the oracle's K (Sec. II, Eqs. 3-4).
 """
 import os
 import sys
@@ -45,10 +48,10 @@ def networks():
     ]
 
 
-def make_ctx(persist: bool):
-    """A context created with or without persistent launches."""
+def make_ctx(mode: int):
+    """A context created with RN_PERSIST=mode (0: one launch per round)."""
     old = os.environ.get("RN_PERSIST")
-    os.environ["RN_PERSIST"] = "1" if persist else "0"
+    os.environ["RN_PERSIST"] = str(int(mode))
     try:
         return B.Context(0)
     finally:
@@ -58,10 +61,10 @@ def make_ctx(persist: bool):
             os.environ["RN_PERSIST"] = old
 
 
-def solve_all(persist: bool, batched: bool):
-    """Results and pressures of every network, from a context created with or
-    without persistent launches."""
-    c = make_ctx(persist)
+def solve_all(mode: int, batched: bool):
+    """Results and pressures of every network, from a context created with
+    RN_PERSIST=mode."""
+    c = make_ctx(mode)
     try:
         sets = networks()
         Ps = [np.zeros(net.shape) for net, _, _ in sets]
@@ -81,30 +84,33 @@ def reference():
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     say("one launch per round: solo solves")
-    return solve_all(persist=False, batched=False)
+    return solve_all(mode=0, batched=False)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
 @pytest.mark.parametrize("batched", [False, True])
-def test_persistent_bit_identical(reference, batched):
+def test_persistent_bit_identical(reference, batched, mode):
     ref_res, ref_P, ref_launches = reference
-    say(f"persistent launches: {'batch' if batched else 'solo solves'}")
-    res, Ps, launches = solve_all(persist=True, batched=batched)
+    say(f"persistent launches (RN_PERSIST={mode}): {'batch' if batched else 'solo solves'}")
+    res, Ps, launches = solve_all(mode=mode, batched=batched)
     for k, (a, b, Pa, Pb) in enumerate(zip(ref_res, res, ref_P, Ps)):
         for f in FIELDS:
             assert getattr(a, f) == getattr(b, f), (k, f, getattr(a, f), getattr(b, f))
         assert Pa.tobytes() == Pb.tobytes(), k
-    if not batched:
-        # one persistent launch per chunk and kind instead of one per round
+    if not batched and mode == 1:
+        # one persistent launch per chunk and kind instead of one per round (with
+        # mode 2 the large FP64 network keeps one launch per round)
         assert launches < ref_launches / 4, (launches, ref_launches)
     say(f"persistent {'batch' if batched else 'solo'}: {launches} launches against {ref_launches}")
 
 
-def test_persistent_served_and_oracle(reference, oracle_mod):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_persistent_served_and_oracle(reference, oracle_mod, mode):
     """Served stream on persistent launches: solo bits, and K against the oracle."""
     import time
     ref_res, ref_P, _ = reference
     sets = networks()
-    c = make_ctx(True)
+    c = make_ctx(mode)
     try:
         Ps = [np.zeros(net.shape) for net, _, _ in sets]
         probs = [B.problem(net, p_out=P) for (net, _, _), P in zip(sets, Ps)]
