@@ -55,7 +55,8 @@ def _load():
         lib.rno_mask_uf.argtypes = common + [u8p, C.POINTER(i64)]
         lib.rno_solve.argtypes = common + [C.c_double, i64, C.c_int, C.c_int, dp, u8p, C.POINTER(_Result)]
         lib.rno_check_pressure.argtypes = common + [dp, dp]
-        for f in (lib.rno_mask_bfs, lib.rno_mask_uf, lib.rno_solve, lib.rno_check_pressure):
+        lib.rno_backbone.argtypes = common + [u8p, C.POINTER(i64), C.POINTER(i64)]
+        for f in (lib.rno_mask_bfs, lib.rno_mask_uf, lib.rno_solve, lib.rno_check_pressure, lib.rno_backbone):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -122,6 +123,19 @@ def mask_uf(net) -> tuple:
     if st:
         raise OracleError(st)
     return out, int(nl.value)
+
+
+def backbone(net) -> tuple:
+    """(mask, n_live, n_backbone): the mask of mask_bfs with bit3 (8) set on
+    the interior nodes of the backbone (nodes on a simple inlet-outlet path),
+    by Hopcroft and Tarjan's biconnected components."""
+    keep, a = _args(*_net_args(net))
+    out = np.zeros(net.shape, dtype=np.uint8)
+    nl, nb = C.c_int64(0), C.c_int64(0)
+    st = _load().rno_backbone(*a, out.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(nl), C.byref(nb))
+    if st:
+        raise OracleError(st)
+    return out, int(nl.value), int(nb.value)
 
 
 X0_LINEAR, X0_ZERO = 0, 1

@@ -241,3 +241,62 @@ def pressure_error_bound(R: np.ndarray, E_field: float, G_star: float, rel_round
     """
     excess = max(E_field - G_star, 0.0) + rel_round * abs(G_star)
     return np.sqrt(R * excess)
+
+
+def backbone_bruteforce(net: Network) -> np.ndarray:
+    """Backbone by vertex cuts (Menger's theorem), on tiny lattices.
+
+    The inlet face is merged into one vertex S and the outlet face into T, and
+    a vertex Z is joined to both. An interior node v lies on a simple S-T path
+    exactly when two v-Z paths share no vertex but v and Z (one through S, the
+    other through T), that is, when v reaches Z and still does after the
+    removal of any single other vertex. Returns a boolean array of the node
+    shape. Cost O(V^2 (V + E)): a few dozen nodes.
+    """
+    I, J, Gv = bond_list(net)
+    f = faces(net)
+    n = net.n
+    S, T, Z = n, n + 1, n + 2
+    adj = [set() for _ in range(n + 3)]
+
+    def vert(a):
+        return a if f[a] == 0 else (S if f[a] == 1 else T)
+
+    for a, b, g in zip(I, J, Gv):
+        if g <= 0 or (f[a] != 0 and f[b] != 0):
+            continue
+        A, B = vert(a), vert(b)
+        adj[A].add(B)
+        adj[B].add(A)
+    for v in (S, T):
+        adj[v].add(Z)
+        adj[Z].add(v)
+
+    def reaches(v, removed):
+        seen = {v, removed}
+        stack = [v]
+        while stack:
+            u = stack.pop()
+            for w in adj[u]:
+                if w == Z:
+                    return True
+                if w not in seen:
+                    seen.add(w)
+                    stack.append(w)
+        return False
+
+    out = np.zeros(n, dtype=bool)
+    for v in range(n):
+        if f[v] != 0 or not adj[v] or not reaches(v, -1):
+            continue
+        out[v] = all(reaches(v, a) for a in range(n + 2) if a != v)
+    return out.reshape(net.shape)
+
+
+def bond_currents(net: Network, P: np.ndarray):
+    """(i, j, g, g (P_i - P_j)) for every occupied bond of the lattice."""
+    I, J, Gv = bond_list(net)
+    p = np.asarray(P, dtype=np.float64).ravel()
+    occ = Gv > 0
+    I, J, Gv = I[occ], J[occ], Gv[occ]
+    return I, J, Gv, Gv * (p[I] - p[J])
