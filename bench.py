@@ -56,6 +56,10 @@ MULTI = {
     "fbmgen": "network generation (Eqs. 1-2, Table I's task): FBM node field by Fourier filtering, bonds and "
               "i.i.d. dilution for 2D 2048x2048 and 3D 256^3, on the GPU (random numbers resident in HBM) "
               "and with numpy on one core",
+    "backbone": "backbone of the spanning cluster (rn_build_backbone, bonds resident in HBM) of the 2048^2 FBM "
+                "network (occupancy 0.6), the 256^3 layered network (occupancy 0.27) and a 2048^2 RRN at "
+                "p = 0.52 (Sec. VI, near p_c = 1/2), against the oracle's depth-first search on one core; "
+                "the RRN is also solved (mixed, 1e-8) with and without its dangling ends",
 }
 
 
@@ -203,7 +207,7 @@ def main():
 
     if args.workload in MULTI:
         run = {"batch512": batch_bench, "serve": serve_bench, "aniso": aniso_bench,
-               "fbmgen": fbmgen_bench}[args.workload]
+               "fbmgen": fbmgen_bench, "backbone": backbone_bench}[args.workload]
         out = run(args, B, I, np)
         print(json.dumps(out), flush=True)
         return
@@ -687,6 +691,65 @@ def fbmgen_bench(args, B, I, np):
     out = _contract(args, total_n / total_t, "nodes/s", total_t, args.steps,
                     {"workload": MULTI["fbmgen"], "inputs": "random numbers resident in HBM"}, dtype="f64")
     out["metric"] = "network generation nodes/s (FBM field + bonds + dilution)"
+    out["cases"] = rows
+    return out
+
+
+def backbone_bench(args, B, I, np):
+    """Lattice nodes per second of rn_build_backbone (mask + backbone), the
+    oracle's Hopcroft-Tarjan search timed beside it on one core."""
+    import torch
+
+    import oracle
+    ctx = B.Context(0)
+    nets = {"2D 2048^2 FBM occ 0.6": I.workload_fbm_2d_2048(),
+            "3D 256^3 layered occ 0.27": I.workload_strat_3d_256(),
+            "2D 2048^2 RRN p 0.52": I.iid_network(2, 2048, 2048, 1, sigma=0.0, occupancy=0.52, index=7)}
+    rows, total_n, total_t = {}, 0, 0.0
+    for label, net in nets.items():
+        gd = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in net.g]
+        m = torch.zeros(net.shape, dtype=torch.uint8, device="cuda")
+        pr = B.problem(dim=net.dim, nx=net.nx, ny=net.ny, nz=net.nz, axis=net.axis, g=gd, mask_out=m)
+        walls = []
+        for it in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            nl, nb = ctx.build_backbone(pr)
+            torch.cuda.synchronize()
+            if it >= args.warmup:
+                walls.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        ref, nlr, nbr = oracle.backbone(net)
+        t_cpu = time.perf_counter() - t
+        same = bool(np.array_equal(m.cpu().numpy(), ref))
+        row = {"nodes": net.n, "n_live": nl, "n_backbone": nb, "backbone_fraction_of_live": round(nb / max(nl, 1), 4),
+               "gpu_ms": round(1e3 * min(walls), 3), "oracle_s": round(t_cpu, 3),
+               "gpu_nodes_per_s": round(net.n / min(walls)), "speedup_vs_oracle": round(t_cpu / min(walls), 1),
+               "mask_equals_oracle": same}
+        if "RRN" in label:
+            M = m.cpu().numpy()
+            dangling = M == 3
+            gp = [np.array(a, copy=True) for a in net.g]
+            for k in range(net.dim):
+                gp[k][dangling] = 0.0
+                gp[k][np.roll(dangling, -1, axis=net.dim - 1 - k)] = 0.0
+            pruned = I.Network(net.dim, net.nx, net.ny, net.nz, gp, net.axis)
+            for name, n_ in (("full", net), ("backbone_only", pruned)):
+                t = time.perf_counter()
+                r, _, _ = B.solve_network(ctx, n_, B.RN_MIXED, args.tol)
+                row[f"solve_{name}"] = {"K": r.K, "iters": int(r.iters), "converged": bool(r.converged),
+                                        "s": round(time.perf_counter() - t, 3)}
+        rows[label] = row
+        total_n += net.n
+        total_t += min(walls)
+        print(f"[bench] backbone {label}: gpu {1e3 * min(walls):.1f} ms, oracle {t_cpu:.2f} s, "
+              f"live {nl} backbone {nb}, equal {same}", file=sys.stderr, flush=True)
+        del gd, m
+        torch.cuda.empty_cache()
+    ctx.close()
+    out = _contract(args, total_n / total_t, "nodes/s", total_t, args.steps,
+                    {"workload": MULTI["backbone"], "inputs": "bonds resident in HBM"}, dtype="int32")
+    out["metric"] = "backbone nodes/s (connectivity mask + biconnected block of the inlet-outlet edge)"
     out["cases"] = rows
     return out
 

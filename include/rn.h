@@ -231,6 +231,29 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
 int rn_build_mask_noalloc(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out);
 
 /*
+ * Backbone of the sample-spanning cluster. Near the percolation threshold
+ * (Sec. VI: the RRN with q -> q_c) most live nodes sit on dangling ends,
+ * branches and loops that meet the rest of the cluster at one node and carry
+ * no flow. The paper does not define the backbone; here it is the textbook
+ * one: the interior nodes that lie on some path from an inlet-face node to an
+ * outlet-face node visiting no node twice. Equivalently, with each face
+ * contracted to one vertex and an edge added between the two, the nodes of
+ * the biconnected component holding that edge. Computed on the device
+ * (a breadth-first spanning tree and Tarjan and Vishkin's joins); the result
+ * does not depend on the order in which the device visits nodes.
+ * Writes prob->mask_out (required): the mask of rn_build_mask with bit3 (8)
+ * set on backbone nodes, so backbone nodes are 11 and other live nodes stay
+ * 3. *n_live_out and *n_backbone_out (nullable) receive the counts. Removing
+ * the live nodes off the backbone changes no flux, and leaves a network whose
+ * live set is the backbone. Memory: prob->mem for g and mask_out; the call
+ * takes about 37 device bytes per node from the context's pool and
+ * synchronises its stream once per 32 levels of the search.
+ * Errors: RN_EINVAL (bad problem, NULL mask_out, nx*ny*nz + 2 >= 2^31, while
+ * the request server runs), RN_ENOMEM, RN_EDEVICE; outputs untouched on error.
+ */
+int rn_build_backbone(rn_ctx *ctx, const rn_problem *prob, int64_t *n_live_out, int64_t *n_backbone_out);
+
+/*
  * Solve one network (Sec. II, Eqs. 3-4): mask, preconditioned CG (opts->precond,
  * Jacobi by default) on the live set from the initial guess opts->x0 (the
  * linear profile along the flow axis by default, or 0) to opts->tol, then

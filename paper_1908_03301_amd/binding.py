@@ -28,7 +28,8 @@ RN_PATH_2D_FULL, RN_PATH_2D_SMALL, RN_PATH_3D = 0, 1, 2
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
             "rn_last_error", "rn_validate", "rn_footprint", "rn_build_mask", "rn_solve", "rn_solve_batch",
             "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds",
-            "rn_build_mask_noalloc", "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset"]
+            "rn_build_mask_noalloc", "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset",
+            "rn_build_backbone"]
 RN_TUNE_QUICK = 1
 RN_NOALLOC_MAX_NODES = 1 << 22
 
@@ -110,6 +111,7 @@ def lib():
         L.rn_footprint.restype = C.c_size_t
         L.rn_build_mask.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
         L.rn_build_mask_noalloc.argtypes = [C.c_void_p, P(rn_problem), P(I64)]
+        L.rn_build_backbone.argtypes = [C.c_void_p, P(rn_problem), P(I64), P(I64)]
         L.rn_solve.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(rn_result)]
         L.rn_solve_batch.argtypes = [C.c_void_p, C.c_int32, P(rn_problem), P(rn_opts), C.c_int32, P(rn_result)]
         L.rn_submit.argtypes = [C.c_void_p, P(rn_problem), P(rn_opts), P(C.c_uint64)]
@@ -127,7 +129,7 @@ def lib():
                                    P(DA3), C.c_double, P(DA3), C.c_int32]
         for f in ("rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream", "rn_build_mask",
                   "rn_build_mask_noalloc", "rn_set_timing", "rn_autotune", "rn_tune_load", "rn_tune_reset",
-                  "rn_solve",
+                  "rn_build_backbone", "rn_solve",
                   "rn_solve_batch", "rn_submit", "rn_poll", "rn_stats", "rn_plan", "rn_fbm_field", "rn_fbm_bonds"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -341,6 +343,14 @@ class Context:
             raise RNError(st, self.last_error())
         return int(nl.value)
 
+    def build_backbone(self, prob: Problem):
+        """rn_build_backbone: (n_live, n_backbone); prob's mask gets bit 3 on backbone nodes."""
+        nl, nb = C.c_int64(0), C.c_int64(0)
+        st = lib().rn_build_backbone(self.h, C.byref(self._own(prob).c), C.byref(nl), C.byref(nb))
+        if st:
+            raise RNError(st, self.last_error())
+        return int(nl.value), int(nb.value)
+
     def solve(self, prob: Problem, o: Optional[rn_opts] = None, check: bool = True) -> rn_result:
         res = rn_result()
         st = lib().rn_solve(self.h, C.byref(self._own(prob).c), C.byref(o) if o is not None else None, C.byref(res))
@@ -442,6 +452,17 @@ def rn_build_mask(ctx: Context, prob: Problem) -> int:
 
 def rn_build_mask_noalloc(ctx: Context, prob: Problem) -> int:
     return ctx.build_mask_noalloc(prob)
+
+
+def rn_build_backbone(ctx: Context, prob: Problem):
+    return ctx.build_backbone(prob)
+
+
+def backbone_network(ctx: Context, net):
+    """Host-memory convenience: (mask with bit 3 on the backbone, n_live, n_backbone)."""
+    M = np.zeros(net.shape, dtype=np.uint8)
+    nl, nb = ctx.build_backbone(problem(net, mask_out=M))
+    return M, nl, nb
 
 
 def rn_solve(ctx: Context, prob: Problem, o: Optional[rn_opts] = None) -> rn_result:

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librn.so")
-SOURCES = ["rn_kernels.hip", "rn_engine.cpp", "rn_api.cpp", "rn_fbm.hip"]
+SOURCES = ["rn_kernels.hip", "rn_engine.cpp", "rn_api.cpp", "rn_fbm.hip", "rn_backbone.hip"]
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

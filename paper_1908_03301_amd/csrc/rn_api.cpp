@@ -479,7 +479,7 @@ int rn_create(int device, size_t budget, rn_ctx **out)
     ctx->stream = ctx->own;
     if (ctx->engine.init(ctx->stream, &ctx->err)) return fail();
     ctx->engine_ok = true;
-    if (hipHostMalloc((void **)&ctx->h_small, 8 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void **)&ctx->h_small, 32 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
         return fail();
     // this device's copy of the static scratch of rn_build_mask_noalloc
     if (noalloc_setup(device) != hipSuccess) return fail();
@@ -640,6 +640,76 @@ int rn_build_mask(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out)
                        ctx->stream) != hipSuccess)
         return done(RN_EDEVICE);
     if (n_live_out) *n_live_out = (int64_t)hc[0];
+    return done(RN_OK);
+}
+
+int rn_build_backbone(rn_ctx *ctx, const rn_problem *p, int64_t *n_live_out, int64_t *n_backbone_out)
+{
+    if (!ctx) return RN_EINVAL;
+    int st = check_shape(p);
+    if (st) return st;
+    if (!p->mask_out) return RN_EINVAL;
+    if (p->mem == RN_MEM_HOST && !host_values_ok(p)) return RN_EINVAL;
+    static_assert(kBackboneStage <= 64, "level offsets staged in the 32-word pinned buffer");
+    const int64_t n = p->nx * p->ny * p->nz;
+    if (n + 2 > (int64_t)INT32_MAX) return RN_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->call_mu);
+    if (ctx->server) return RN_EINVAL;        // the server owns the stream once started
+    RN_TRY(hipSetDevice(ctx->device));
+    // FP64 bonds (host input), the mask, the mask's labels (8 bytes per node),
+    // the counters, then the backbone's own arrays
+    auto a256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t nn = (size_t)n;
+    const bool copy_g = p->mem == RN_MEM_HOST;
+    const size_t off_g = 0, off_mask = off_g + a256(copy_g ? 8 * p->dim * nn : 0), off_lab = off_mask + a256(nn),
+                 off_cnt = off_lab + a256(8 * nn), off_bb = off_cnt + 256,
+                 total = off_bb + backbone_scratch_bytes(n);
+    hipError_t he;
+    char *base = (char *)ctx->pool.alloc(total, &he);
+    if (!base) return RN_ENOMEM;
+    const Lat lat = make_lat(p);
+    const double *gd[3] = {nullptr, nullptr, nullptr};
+    auto done = [&](int r) {
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->pool.free(base);
+        return r;
+    };
+    if (copy_g) {
+        for (int k = 0; k < p->dim; ++k) {
+            double *dst = (double *)(base + off_g) + (size_t)k * nn;
+            if (hipMemcpyAsync(dst, p->g[k], 8 * nn, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+                return done(RN_EDEVICE);
+            gd[k] = dst;
+        }
+    } else {
+        for (int k = 0; k < p->dim; ++k) gd[k] = p->g[k];
+    }
+    unsigned long long *cnt = (unsigned long long *)(base + off_cnt);
+    unsigned long long *hc = ctx->h_small;
+    uint8_t *mask = (uint8_t *)(base + off_mask);
+    if (launch_clear_u64(cnt, 4, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (!copy_g && launch_validate(lat, gd, cnt + 1, ctx->stream) != hipSuccess) return done(RN_EDEVICE);
+    if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    if (hc[1] != 0) return done(RN_EINVAL);
+    if (launch_mask(lat, gd, (int *)(base + off_lab), (unsigned *)(base + off_lab + 4 * nn), mask, nullptr, cnt, true,
+                    ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    // with fewer than 3 planes on the flow axis there is no interior node
+    const int n_axis = p->axis == 0 ? (int)p->nx : (p->axis == 1 ? (int)p->ny : (int)p->nz);
+    if (n_axis >= 3 && launch_backbone(lat, gd, mask, base + off_bb, cnt + 2, (int *)ctx->h_small, nullptr,
+                                       ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    const int64_t n_live = (int64_t)hc[0], n_bb = (int64_t)hc[2];
+    if (hipMemcpyAsync(p->mask_out, mask, nn, p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                       ctx->stream) != hipSuccess)
+        return done(RN_EDEVICE);
+    if (n_live_out) *n_live_out = n_live;
+    if (n_backbone_out) *n_backbone_out = n_bb;
     return done(RN_OK);
 }
 

@@ -132,6 +132,19 @@ hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st);
 // g[i] in [1, 2) from a hash of i and salt (the networks of the launch-shape trials)
 hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st);
 
+// Backbone (rn_backbone.hip): with `mask` the connectivity mask of the
+// lattice, set bit 3 on every interior node of the backbone and add their
+// number to *n_backbone (a device counter). `scratch` holds
+// backbone_scratch_bytes(n) device bytes; h_stage is pinned host memory of
+// kBackboneStage ints for the level offsets the breadth-first search reads
+// back (one synchronisation of `st` per kBackboneStage - 2 levels). Needs
+// n + 2 < 2^31 and at least 3 planes on the flow axis. *depth_out (nullable)
+// receives the number of levels of the search.
+constexpr int kBackboneStage = 34;
+size_t backbone_scratch_bytes(int64_t n);
+hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask, void *scratch,
+                           unsigned long long *n_backbone, int *h_stage, int *depth_out, hipStream_t st);
+
 // Static scratch of the allocation-free mask entry point: 8 bytes per node
 // (union-find parents and component flags) for up to kNoAllocMaxNodes nodes,
 // then four 8-byte counters. noalloc_setup(device), called with `device`

@@ -244,7 +244,8 @@ struct rn_ctx {
     rn_server *server = nullptr;
     void *fbm_plans = nullptr;      // FFT plans of the last generated grid (rn_fbm.hip)
     size_t active_cap = 0;          // RN_ACTIVE_BYTES: cap on the device bytes of networks in flight (0: none)
-    unsigned long long *h_small = nullptr;   // pinned, 8 words: counters read back by rn_build_mask_noalloc
+    unsigned long long *h_small = nullptr;   // pinned, 32 words: counters read back by rn_build_mask_noalloc,
+                                             // level offsets of rn_build_backbone
 };
 
 namespace rn {

@@ -211,6 +211,8 @@ def test_null_context_is_rejected(lib):
     res = B.rn_result()
     assert lib.rn_solve(None, C.byref(_prob().c), None, C.byref(res)) == B.RN_EINVAL
     assert lib.rn_build_mask(None, C.byref(_prob().c), None) == B.RN_EINVAL
+    assert lib.rn_build_backbone(None, C.byref(_prob().c), None, None) == B.RN_EINVAL
+    assert lib.rn_build_backbone(None, None, None, None) == B.RN_EINVAL
     assert lib.rn_destroy(None) == B.RN_OK
 
 

@@ -18,7 +18,7 @@ import pytest
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(ROOT, "paper_1908_03301_amd", "csrc")
-SOURCES = ["rn_api.cpp", "rn_engine.cpp", "rn_kernels.hip", "rn_fbm.hip"]
+SOURCES = ["rn_api.cpp", "rn_engine.cpp", "rn_kernels.hip", "rn_fbm.hip", "rn_backbone.hip"]
 HOST_SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-omit-frame-pointer"]
 
