@@ -76,6 +76,16 @@ extern "C" {
                            with no-flow sides (default) */
 #define RN_X0_ZERO 1    /* 0 */
 
+/* rn_opts.flags */
+#define RN_OPT_BACKBONE 1  /* solve on the backbone (rn_build_backbone): the dangling ends, which
+                              carry no current, are cut out before the CG and each takes the
+                              pressure of the backbone node it hangs from afterwards. K, G, the
+                              fluxes and every pressure are those of the whole network; the CG
+                              runs on fewer nodes and, near the percolation threshold, in fewer
+                              iterations. rn_solve and rn_solve_batch only (rn_submit: RN_EINVAL).
+                              mask_out receives rn_build_backbone's mask; rn_result.n_live counts
+                              the whole live set and n_backbone the backbone. */
+
 /* rn_problem.mem */
 #define RN_MEM_HOST 0
 #define RN_MEM_DEVICE 1
@@ -116,7 +126,7 @@ typedef struct {
                            recurrence then continues from the FP64 residual (reliable update).
                            Ignored by RN_FP64. Must lie in [0, 1). */
     int32_t x0;         /* RN_X0_LINEAR (default) or RN_X0_ZERO */
-    int32_t reserved;   /* must be 0 */
+    int32_t flags;      /* 0 (default) or RN_OPT_BACKBONE; other bits: RN_EINVAL */
 } rn_opts;
 
 /* Outcome of one solve. */
@@ -139,6 +149,7 @@ typedef struct {
     double t_loop_s;    /* device time from the start of this network's iterations to the
                            end of its last round */
     double t_total_s;   /* host wall time from the call (or rn_submit) to completion */
+    int64_t n_backbone; /* backbone nodes with RN_OPT_BACKBONE, else 0 */
 } rn_result;
 
 /* Library version, 100 * major + minor. */
@@ -183,7 +194,7 @@ const char *rn_last_error(rn_ctx *ctx);
 
 /*
  * Check a problem and options without touching a device: shapes, axis,
- * pointers, flags, reserved fields, options and, for RN_MEM_HOST, every
+ * pointers, flags, options and, for RN_MEM_HOST, every
  * conductance the lattice uses (finite, >= 0). opts may be NULL (defaults). Returns RN_OK or
  * RN_EINVAL; the same checks open rn_solve and rn_build_mask.
  */

@@ -298,19 +298,170 @@ void server_main(rn_ctx *ctx)
     }
 }
 
+// ------------------------------------------------------------------ solves on the backbone
+// RN_OPT_BACKBONE: before the engine sees the network, its bonds are copied
+// to the device, the mask and the backbone are built, the pieces of dangling
+// nodes and the backbone node each hangs from are found, and every bond with
+// a dangling end is zeroed in the copy. The engine then solves that copy
+// (device bonds, device pressures); afterwards the dangling nodes take the
+// pressure of their backbone node and the outputs go to the caller.
+struct BackbonePrep {
+    rn_problem q{};               // the problem the engine solves
+    char *aux = nullptr;          // pruned bonds | mask | uf | att | pressures (host callers) | counters
+    uint8_t *mask = nullptr;
+    int *uf = nullptr, *att = nullptr;
+    int64_t n_live = 0, n_backbone = 0;
+};
+
+static size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t backbone_aux_bytes(const rn_problem *p)
+{
+    const size_t n = (size_t)(p->nx * p->ny * p->nz);
+    return a256(8 * (size_t)p->dim * n) + a256(n) + 2 * a256(4 * n) + a256(8 * n) + 256;
+}
+
+static size_t backbone_transient_bytes(const rn_problem *p)
+{
+    const int64_t n = p->nx * p->ny * p->nz;
+    return a256(8 * (size_t)n) + backbone_scratch_bytes(n);
+}
+
+// Caller holds call_mu and the device is current; the server is not running.
+static int backbone_prepare(rn_ctx *ctx, const rn_problem *p, BackbonePrep *b)
+{
+    const int64_t n = p->nx * p->ny * p->nz;
+    if (n + 2 > (int64_t)INT32_MAX) return RN_EINVAL;
+    const size_t nn = (size_t)n;
+    hipError_t he;
+    b->aux = (char *)ctx->pool.alloc(backbone_aux_bytes(p), &he);
+    if (!b->aux) return RN_ENOMEM;
+    char *tr = (char *)ctx->pool.alloc(backbone_transient_bytes(p), &he);
+    if (!tr) return RN_ENOMEM;
+    hipStream_t st = ctx->stream;
+    char *q = b->aux;
+    double *g[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < p->dim; ++k) g[k] = (double *)q + (size_t)k * nn;
+    q += a256(8 * (size_t)p->dim * nn);
+    b->mask = (uint8_t *)q;
+    q += a256(nn);
+    b->uf = (int *)q;
+    q += a256(4 * nn);
+    b->att = (int *)q;
+    q += a256(4 * nn);
+    double *P = (double *)q;
+    q += a256(8 * nn);
+    unsigned long long *cnt = (unsigned long long *)q;
+    unsigned long long *hc = ctx->h_small;
+    const Lat lat = make_lat(p);
+    const double *gc[3] = {g[0], g[1], g[2]};
+    auto fail = [&](int r) {
+        (void)hipStreamSynchronize(st);
+        ctx->pool.free(tr);
+        return r;
+    };
+    for (int k = 0; k < p->dim; ++k)
+        if (hipMemcpyAsync(g[k], p->g[k], 8 * nn, p->mem == RN_MEM_HOST ? hipMemcpyHostToDevice
+                                                                           : hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return fail(RN_EDEVICE);
+    if (launch_clear_u64(cnt, 4, st) != hipSuccess) return fail(RN_EDEVICE);
+    if (p->mem == RN_MEM_DEVICE) {
+        if (launch_validate(lat, gc, cnt + 1, st) != hipSuccess) return fail(RN_EDEVICE);
+        if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return fail(RN_EDEVICE);
+        if (hc[1] != 0) return fail(RN_EINVAL);
+    }
+    if (launch_mask(lat, gc, (int *)tr, (unsigned *)(tr + 4 * nn), b->mask, nullptr, cnt, true, st) != hipSuccess)
+        return fail(RN_EDEVICE);
+    const int n_axis = p->axis == 0 ? (int)p->nx : (p->axis == 1 ? (int)p->ny : (int)p->nz);
+    if (n_axis >= 3 && launch_backbone(lat, gc, b->mask, tr + a256(8 * nn), cnt + 2, (int *)ctx->h_small, nullptr,
+                                       st) != hipSuccess)
+        return fail(RN_EDEVICE);
+    if (launch_backbone_prune(lat, g, b->mask, b->uf, b->att, st) != hipSuccess) return fail(RN_EDEVICE);
+    if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return fail(RN_EDEVICE);
+    b->n_live = (int64_t)hc[0];
+    b->n_backbone = (int64_t)hc[2];
+    ctx->pool.free(tr);
+    b->q = *p;
+    for (int k = 0; k < 3; ++k) b->q.g[k] = k < p->dim ? g[k] : nullptr;
+    b->q.mem = RN_MEM_DEVICE;
+    b->q.mask_out = nullptr;
+    b->q.p_out = p->p_out ? (p->mem == RN_MEM_DEVICE ? p->p_out : P) : nullptr;
+    return RN_OK;
+}
+
+// Caller holds call_mu and the device is current.
+static int backbone_finish(rn_ctx *ctx, const rn_problem *p, BackbonePrep *b, rn_result *r)
+{
+    const size_t nn = (size_t)(p->nx * p->ny * p->nz);
+    hipStream_t st = ctx->stream;
+    const Lat lat = make_lat(p);
+    const hipMemcpyKind kind = p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (p->p_out) {
+        RN_TRY(launch_backbone_fill(lat, b->mask, b->uf, b->att, b->q.p_out, st));
+        if (p->mem == RN_MEM_HOST) RN_TRY(hipMemcpyAsync(p->p_out, b->q.p_out, 8 * nn, kind, st));
+    }
+    if (p->mask_out) RN_TRY(hipMemcpyAsync(p->mask_out, b->mask, nn, kind, st));
+    RN_TRY(hipStreamSynchronize(st));
+    r->n_live = b->n_live;
+    r->n_backbone = b->n_backbone;
+    return RN_OK;
+}
+
 int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opts *opts, int32_t n_opts,
                rn_result *out)
 {
     if (!ctx || !out || !probs || count < 1) return RN_EINVAL;
     if (!(n_opts == 0 || n_opts == 1 || n_opts == count)) return RN_EINVAL;
     if (n_opts > 0 && !opts) return RN_EINVAL;
+    auto opts_of = [&](int i) { return n_opts == 0 ? nullptr : (n_opts == 1 ? opts : opts + i); };
+    // solves on the backbone: check, then prune their bonds before the engine sees them
+    std::vector<BackbonePrep> bb((size_t)count);
+    std::vector<char> on_bb((size_t)count, 0);
+    std::vector<rn_problem> eff(probs, probs + count);
+    auto free_bb = [&]() {
+        for (BackbonePrep &b : bb)
+            if (b.aux) {
+                ctx->pool.free(b.aux);
+                b.aux = nullptr;
+            }
+    };
+    bool any_bb = false;
+    for (int i = 0; i < count; ++i) {
+        const rn_opts *o = opts_of(i);
+        if (!o || !(o->flags & RN_OPT_BACKBONE)) continue;
+        int st = check_shape(probs + i);
+        if (!st) st = check_opts(o);
+        if (!st && probs[i].mem == RN_MEM_HOST && !host_values_ok(probs + i)) st = RN_EINVAL;
+        if (!st && ctx->server) st = RN_EINVAL;      // the server owns the stream
+        if (st) return st;
+        on_bb[(size_t)i] = 1;
+        any_bb = true;
+    }
+    if (any_bb) {
+        std::lock_guard<std::mutex> lk(ctx->call_mu);
+        if (ctx->server) return RN_EINVAL;
+        if (hipSetDevice(ctx->device) != hipSuccess) return RN_EDEVICE;
+        for (int i = 0; i < count; ++i) {
+            if (!on_bb[(size_t)i]) continue;
+            const int st = backbone_prepare(ctx, probs + i, &bb[(size_t)i]);
+            if (st) {
+                free_bb();
+                return st;
+            }
+            eff[(size_t)i] = bb[(size_t)i].q;
+        }
+    }
     std::vector<Net *> nets((size_t)count, nullptr);
     for (int i = 0; i < count; ++i) {
-        const rn_opts *o = n_opts == 0 ? nullptr : (n_opts == 1 ? opts : opts + i);
-        int st = make_net(ctx, probs + i, o, &nets[i]);
+        int st = make_net(ctx, &eff[(size_t)i], opts_of(i), &nets[i]);
         if (st) {
             for (Net *n : nets)
                 if (n) release_net(n);
+            free_bb();
             return st;
         }
     }
@@ -348,6 +499,14 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
         if (nets[i]->base) ctx->pool.free(nets[i]->base);
         release_net(nets[i]);
     }
+    if (any_bb && !r) {
+        // outputs of the solves on the backbone (those that ran: RN_OK or RN_ENOCONV)
+        std::lock_guard<std::mutex> lk(ctx->call_mu);
+        for (int i = 0; i < count && !r; ++i)
+            if (on_bb[(size_t)i] && (out[i].status == RN_OK || out[i].status == RN_ENOCONV))
+                r = backbone_finish(ctx, probs + i, &bb[(size_t)i], out + i);
+    }
+    free_bb();
     return r ? r : first;
 }
 
@@ -554,7 +713,11 @@ size_t rn_footprint(const rn_problem *p, const rn_opts *o)
     if (check_shape(p) != RN_OK) return 0;
     rn_opts d;
     rn_opts_default(&d);
-    return make_layout(p, o ? o : &d).total;
+    size_t bytes = make_layout(p, o ? o : &d).total;
+    if (o && (o->flags & RN_OPT_BACKBONE))   // the pruned copy and its maps, plus the larger of the
+        bytes += backbone_aux_bytes(p) +      // backbone's transient arrays and the solve itself
+                 (backbone_transient_bytes(p) > bytes ? backbone_transient_bytes(p) - bytes : 0);
+    return bytes;
 }
 
 int rn_plan(const rn_problem *p, const rn_opts *opts, rn_plan_t *out)
@@ -769,6 +932,7 @@ int rn_solve_batch(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn
 int rn_submit(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, uint64_t *ticket_out)
 {
     if (!ctx || !ticket_out) return RN_EINVAL;
+    if (opts && (opts->flags & RN_OPT_BACKBONE)) return RN_EINVAL;   // rn_solve / rn_solve_batch only
     Net *net = nullptr;
     int st = make_net(ctx, p, opts, &net);
     if (st) return st;

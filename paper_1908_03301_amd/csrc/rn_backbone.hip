@@ -421,6 +421,94 @@ __global__ void bb_apply(uint8_t *mask, const uint8_t *on, int n, unsigned long 
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
 }
 
+// ---------------------------------------------------------------- solves on the backbone
+// With the backbone marked (11) and the other live nodes dangling (3), a solve
+// may cut the dangling ends out: they carry no current, so the backbone's
+// pressures and every flux are unchanged. Each connected piece of dangling
+// nodes meets the backbone at exactly one node a (a piece joined to two
+// backbone nodes, or to a face and the backbone, would lie on a path that
+// visits no node twice) and, carrying no current, sits at a's pressure.
+
+// Pieces of dangling nodes: union over occupied bonds between two of them.
+__global__ void bb_piece_union(BbGraph G, int *uf, int *att)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
+        if (G.mask[i] != 3) continue;
+        att[i] = -1;
+        int c[3];
+        coords(G, i, c);
+        for (int d = 1; d < 2 * G.dim; d += 2) {           // each bond once, from its -k end
+            const int w = bb_nbr(G, i, c, d);               // a dangling neighbour (mask 3), or S, T, -1
+            if (w >= 0 && w < G.n) uf_union(uf, i, w);
+        }
+    }
+}
+
+// The backbone node each piece hangs from, stored at the piece's root (every
+// dangling node next to it writes the same index).
+__global__ void bb_piece_attach(BbGraph G, int *uf, int *att)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
+        if (G.mask[i] != 3) continue;
+        int c[3];
+        coords(G, i, c);
+        for (int d = 0; d < 2 * G.dim; ++d) {
+            double gij = 0.0;
+            const int j = lat_step(G, i, c, d, &gij);
+            if (j >= 0 && gij > 0.0 && G.mask[j] == 11) att[uf_find(uf, i)] = j;
+        }
+    }
+}
+
+// Zero every bond with a dangling end (in place: entry g[k][i] is the bond
+// from i to its +k neighbour).
+__global__ void bb_prune(BbGraph G, double *g0, double *g1, double *g2)
+{
+    double *gk[3] = {g0, g1, g2};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += gridDim.x * blockDim.x) {
+        int c[3];
+        coords(G, i, c);
+        const bool di = G.mask[i] == 3;
+        for (int k = 0; k < G.dim; ++k) {
+            double gij = 0.0;
+            const int j = lat_step(G, i, c, 2 * k + 1, &gij);
+            if (j >= 0 && (di || G.mask[j] == 3)) gk[k][i] = 0.0;
+        }
+    }
+}
+
+// Pressures of the dangling nodes: that of the backbone node their piece hangs from.
+__global__ void bb_fill(const uint8_t *mask, int *uf, const int *att, double *P, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        if (mask[i] != 3) continue;
+        const int a = att[uf_find(uf, i)];
+        if (a >= 0) P[i] = P[a];
+    }
+}
+
+__global__ void bb_iota(int *uf, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) uf[i] = i;
+}
+
+BbGraph graph_of(const Lat &L, const double *const g[3], const uint8_t *mask)
+{
+    BbGraph G;
+    for (int k = 0; k < 3; ++k) G.g[k] = k < L.dim ? g[k] : nullptr;
+    G.mask = mask;
+    G.dim = L.dim;
+    G.axis = L.axis;
+    G.nx = L.nx;
+    G.ny = L.ny;
+    G.nz = L.nz;
+    G.wrap = L.wrap;
+    G.n = (int)L.n;
+    G.S = (int)L.n;
+    G.T = (int)L.n + 1;
+    return G;
+}
+
 int grid_of(int64_t n)
 {
     return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBbBlock - 1) / kBbBlock, 8192));
@@ -454,18 +542,7 @@ hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask
     int *lev_off = (int *)take(4 * ((size_t)V + 40));
     int *tail = (int *)take(256);
 
-    BbGraph G;
-    for (int k = 0; k < 3; ++k) G.g[k] = k < L.dim ? g[k] : nullptr;
-    G.mask = mask;
-    G.dim = L.dim;
-    G.axis = L.axis;
-    G.nx = L.nx;
-    G.ny = L.ny;
-    G.nz = L.nz;
-    G.wrap = L.wrap;
-    G.n = (int)n;
-    G.S = (int)n;
-    G.T = (int)n + 1;
+    const BbGraph G = graph_of(L, g, mask);
 
     hipError_t e;
     bb_init<<<grid_of(V), kBbBlock, 0, st>>>(lev, pdir, nd, pre, uf, on, V, G.S, G.T, order, lev_off, tail);
@@ -522,6 +599,26 @@ hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask
     bb_mark<<<grid_of(nvis - 1), kBbBlock, 0, st>>>(G, 1, nvis, order, pdir, uf, on);
     bb_apply<<<grid_of(n), kBbBlock, 0, st>>>(mask, on, (int)n, n_backbone);
     if (depth_out) *depth_out = depth;
+    return hipGetLastError();
+}
+
+hipError_t launch_backbone_prune(const Lat &L, double *const g[3], const uint8_t *mask, int *uf, int *att,
+                                 hipStream_t st)
+{
+    const double *gc[3] = {g[0], g[1], L.dim == 3 ? g[2] : nullptr};
+    const BbGraph G = graph_of(L, gc, mask);
+    const int gr = grid_of(L.n);
+    bb_iota<<<gr, kBbBlock, 0, st>>>(uf, (int)L.n);
+    bb_piece_union<<<gr, kBbBlock, 0, st>>>(G, uf, att);
+    bb_piece_attach<<<gr, kBbBlock, 0, st>>>(G, uf, att);
+    bb_prune<<<gr, kBbBlock, 0, st>>>(G, g[0], g[1], L.dim == 3 ? g[2] : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_backbone_fill(const Lat &L, const uint8_t *mask, int *uf, const int *att, double *P,
+                                hipStream_t st)
+{
+    bb_fill<<<grid_of(L.n), kBbBlock, 0, st>>>(mask, uf, att, P, (int)L.n);
     return hipGetLastError();
 }
 

@@ -144,6 +144,16 @@ constexpr int kBackboneStage = 34;
 size_t backbone_scratch_bytes(int64_t n);
 hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask, void *scratch,
                            unsigned long long *n_backbone, int *h_stage, int *depth_out, hipStream_t st);
+// With `mask` from launch_backbone (backbone 11, dangling 3): find the pieces
+// of dangling nodes (uf, n ints) and the backbone node each hangs from (att,
+// n ints, at the piece's root), then zero in place every bond of g (device,
+// writable) with a dangling end.
+hipError_t launch_backbone_prune(const Lat &L, double *const g[3], const uint8_t *mask, int *uf, int *att,
+                                 hipStream_t st);
+// After the solve of the pruned network: every dangling node takes the
+// pressure of the backbone node its piece hangs from.
+hipError_t launch_backbone_fill(const Lat &L, const uint8_t *mask, int *uf, const int *att, double *P,
+                                hipStream_t st);
 
 // Static scratch of the allocation-free mask entry point: 8 bytes per node
 // (union-find parents and component flags) for up to kNoAllocMaxNodes nodes,

@@ -78,8 +78,10 @@ int main()
     expect(rn_validate(&p, &bad) == RN_EINVAL, "tol 0");
     bad = o; bad.precision = 5;
     expect(rn_validate(&p, &bad) == RN_EINVAL, "precision 5");
-    bad = o; bad.reserved = 1;
-    expect(rn_validate(&p, &bad) == RN_EINVAL, "reserved field");
+    bad = o; bad.flags = 2;
+    expect(rn_validate(&p, &bad) == RN_EINVAL, "unknown option flag");
+    bad = o; bad.flags = RN_OPT_BACKBONE;
+    expect(rn_validate(&p, &bad) == RN_OK && rn_footprint(&p, &bad) > rn_footprint(&p, &o), "backbone option");
     expect(rn_validate(nullptr, &o) == RN_EINVAL, "NULL problem");
     expect(rn_create(0, 0, nullptr) == RN_EINVAL, "create without an output pointer");
 

@@ -107,12 +107,13 @@ def test_opts_field_offsets_match_header(lib):
 def test_opts_precond_and_initial_guess(lib):
     o = B.rn_opts()
     assert lib.rn_opts_default(C.byref(o)) == B.RN_OK
-    assert o.precond == B.RN_JACOBI and o.x0 == B.RN_X0_LINEAR and o.reserved == 0
+    assert o.precond == B.RN_JACOBI and o.x0 == B.RN_X0_LINEAR and o.flags == 0
     p = _prob()
     for prec in (B.RN_JACOBI, B.RN_NONE):
         for x0 in (B.RN_X0_LINEAR, B.RN_X0_ZERO):
             assert B.rn_validate(p, B.opts(precond=prec, x0=x0)) == B.RN_OK
-    for field, bad in (("precond", 2), ("precond", -1), ("x0", 2), ("x0", -1), ("reserved", 1)):
+    assert B.rn_validate(p, B.opts(backbone=True)) == B.RN_OK
+    for field, bad in (("precond", 2), ("precond", -1), ("x0", 2), ("x0", -1), ("flags", 2), ("flags", -1)):
         o = B.opts()
         setattr(o, field, bad)
         assert B.rn_validate(p, o) == B.RN_EINVAL, field

@@ -122,3 +122,86 @@ def test_backbone_full_size(ctx, oracle_mod, make):
     say(f"live {nl} backbone {nb} (oracle {nlr} {nbr})")
     assert (nl, nb) == (nlr, nbr)
     np.testing.assert_array_equal(M, ref)
+
+
+# ------------------------------------------------------------------ solves on the backbone (RN_OPT_BACKBONE)
+
+TOL = {B.RN_FP64: 1e-10, B.RN_MIXED: 1e-8}
+KBAR = {B.RN_FP64: 1e-9, B.RN_MIXED: 1e-7}
+
+
+def bb_cases():
+    return [
+        ("iid 2D 300x257 p0.55 mixed", I.iid_network(2, 300, 257, 1, occupancy=0.55, index=5100), B.RN_MIXED),
+        ("iid 2D 257x300 p0.53 axis y fp64", I.iid_network(2, 257, 300, 1, occupancy=0.53, index=5101, axis=1),
+         B.RN_FP64),
+        ("fbm 3D 48^3 occ0.35 mixed", I.fbm_network(3, 48, 48, 48, H=0.7, sigma=1.0, occupancy=0.35, index=5105),
+         B.RN_MIXED),
+        ("periodic 2D 200x150 p0.55 mixed", I.iid_network(2, 200, 150, 1, occupancy=0.55, index=5106,
+                                                          periodic=True), B.RN_MIXED),
+        ("periodic 3D 40^3 p0.3 fp64", I.iid_network(3, 40, 40, 40, occupancy=0.3, index=5109, periodic=True),
+         B.RN_FP64),
+        ("nothing spans 2D p0.3 mixed", I.iid_network(2, 200, 200, 1, occupancy=0.3, index=5111), B.RN_MIXED),
+        ("2 planes 2x50 fp64", I.iid_network(2, 2, 50, 1, occupancy=0.9, index=5112), B.RN_FP64),
+    ]
+
+
+@pytest.mark.parametrize("label,net,prec", bb_cases(), ids=[c[0] for c in bb_cases()])
+def test_backbone_option_against_oracle(ctx, oracle_mod, label, net, prec):
+    """K, every pressure and the backbone mask of a solve on the backbone against the oracle's
+    solve of the whole network."""
+    from tests import _pins
+    say(f"RN_OPT_BACKBONE {label}")
+    r, P, M = B.solve_network(ctx, net, prec, TOL[prec], want_pressure=True, want_mask=True, backbone=True)
+    r0, _, _ = B.solve_network(ctx, net, prec, TOL[prec])
+    mref, nl, nb = oracle_mod.backbone(net)
+    ref = oracle_mod.solve(net, tol=1e-13)
+    say(f"{label}: live {r.n_live} backbone {r.n_backbone} K {r.K:.12g} oracle {ref.K:.12g} "
+        f"iters {r0.iters} -> {r.iters}")
+    np.testing.assert_array_equal(M, mref)
+    assert (r.n_live, r.n_backbone) == (nl, nb)
+    assert r.status == 0 and r.converged
+    if nl == 0:
+        assert r.K == pytest.approx(ref.K, rel=1e-12, abs=1e-300) and r.iters == 0
+        return
+    assert r.K == pytest.approx(ref.K, rel=KBAR[prec])
+    # the filled field solves the whole network: its true residual, its energy, its pressures
+    c = oracle_mod.check_pressure(net, P)
+    assert c.rel_resid <= 1.01 * TOL[prec]
+    assert r.G == pytest.approx(c.G_E, rel=1e-9)
+    live = (mref.ravel() & 3) == 3                # live nodes: backbone (11) and dangling (3)
+    R = _pins.face_path_resistance(net).ravel()[live]
+    eps = _pins.pressure_error_bound(R, _pins.energy(net, P), ref.G)
+    err = np.abs(P.ravel()[live] - ref.pressure.ravel()[live])
+    assert np.all(err <= eps), float(np.max(err - eps))
+
+
+def test_backbone_option_device_memory_and_batch(ctx):
+    """Device buffers, and a batch mixing solves on the backbone with plain ones: each result and
+    pressure field equals the same solve made alone."""
+    import torch
+    nets = [I.iid_network(2, 220, 180, 1, occupancy=0.55, index=5140),
+            I.fbm_network(2, 300, 240, 1, H=0.7, sigma=1.5, occupancy=0.6, index=5141),
+            I.iid_network(3, 40, 36, 30, occupancy=0.3, index=5142)]
+    flags = [True, False, True]
+    solo = []
+    for net, bb in zip(nets, flags):
+        solo.append(B.solve_network(ctx, net, B.RN_MIXED, 1e-8, want_pressure=True, want_mask=True, backbone=bb))
+    gs = [[torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in n.g] for n in nets]
+    Ps = [torch.zeros(n.shape, dtype=torch.float64, device="cuda") for n in nets]
+    Ms = [torch.zeros(n.shape, dtype=torch.uint8, device="cuda") for n in nets]
+    probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=n.axis, g=g, p_out=P, mask_out=M)
+             for n, g, P, M in zip(nets, gs, Ps, Ms)]
+    res = ctx.solve_batch(probs, [B.opts(B.RN_MIXED, 1e-8, backbone=bb) for bb in flags])
+    for (r0, P0, M0), r, P, M in zip(solo, res, Ps, Ms):
+        for f in ("status", "converged", "K", "G", "Q_in", "Q_out", "iters", "n_live", "n_backbone"):
+            assert getattr(r0, f) == getattr(r, f), f
+        assert P0.tobytes() == P.cpu().numpy().tobytes()
+        np.testing.assert_array_equal(M0, M.cpu().numpy())
+    assert res[1].n_backbone == 0 and res[0].n_backbone > 0
+
+
+def test_backbone_option_rejected_by_submit(ctx):
+    net = I.iid_network(2, 64, 64, 1, occupancy=0.6, index=5150)
+    with pytest.raises(B.RNError):
+        ctx.submit(B.problem(net), B.opts(B.RN_MIXED, 1e-8, backbone=True))
