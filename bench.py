@@ -59,7 +59,8 @@ MULTI = {
     "backbone": "backbone of the spanning cluster (rn_build_backbone, bonds resident in HBM) of the 2048^2 FBM "
                 "network (occupancy 0.6), the 256^3 layered network (occupancy 0.27) and a 2048^2 RRN at "
                 "p = 0.52 (Sec. VI, near p_c = 1/2), against the oracle's depth-first search on one core; "
-                "the RRN is also solved (mixed, 1e-8) with and without its dangling ends",
+                "then 2048^2 RRNs at p = 0.7, 0.6, 0.55, 0.52 solved (mixed, 1e-8) on the whole live set "
+                "and with RN_OPT_BACKBONE",
 }
 
 
@@ -135,9 +136,10 @@ def copy_ceiling_gbps(mib: int = 1024) -> float:
     return 2 * nbytes / best / 1e9
 
 
-def run_solves(ctx, B, prob_by_axis, precision, tol, steps, warmup, max_iter=2_000_000):
+def run_solves(ctx, B, prob_by_axis, precision, tol, steps, warmup, max_iter=2_000_000, backbone=False,
+               compact=False):
     lat, results = [], []
-    o = B.opts(precision, tol, max_iter=max_iter)
+    o = B.opts(precision, tol, max_iter=max_iter, backbone=backbone, compact=compact)
     import torch
     for it in range(warmup + steps):
         for axis, pr in prob_by_axis:
@@ -178,6 +180,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-iters", type=int, default=60, help="oracle PCG iterations in the CPU sample")
     ap.add_argument("--single-axis", action="store_true", help="solve only the first flow axis (profiling)")
+    ap.add_argument("--options", action="store_true",
+                    help="single-network workloads: also time the mixed solve with RN_OPT_BACKBONE, RN_OPT_COMPACT "
+                         "and both (extra keys; the headline stays the plain solve)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -290,6 +295,25 @@ def main():
         out["axes_batched"] = {"solves_per_s": round(len(probs) / min(walls), 4),
                                "wall_ms": round(1e3 * min(walls), 3),
                                "K": {f"axis{ax}": r.K for (ax, _), r in zip(probs, rb)}}
+
+    if args.options:
+        # the same mixed solves with the backbone and compact options (their setup included)
+        variants = {}
+        for name, bb, cp in (("backbone", True, False), ("compact", False, True), ("backbone_compact", True, True)):
+            lat_v, res_v = run_solves(ctx, B, probs, B.RN_MIXED, args.tol, args.steps, args.warmup, backbone=bb,
+                                      compact=cp)
+            for _, r in res_v:
+                if r["status"] != 0 or not r["converged"]:
+                    raise SystemExit(f"solve failed ({name}): {r}")
+            k = len(wl["axes"])
+            variants[name] = {
+                "solves_per_s": round(len(lat_v) / sum(lat_v), 4),
+                "speedup_vs_plain": round((len(lat_v) / sum(lat_v)) / value, 3),
+                "iters": {f"axis{ax}": r["iters"] for ax, r in res_v[:k]},
+                "n_backbone": {f"axis{ax}": r["n_backbone"] for ax, r in res_v[:k]},
+                "loop_ms": {f"axis{ax}": round(1e3 * r["t_loop_s"], 2) for ax, r in res_v[:k]},
+                "K_rel_diff_vs_plain": max(abs(a[1]["K"] / b[1]["K"] - 1.0) for a, b in zip(res_v[:k], res_m[:k]))}
+        out["options"] = variants
 
     if not args.no_fp64:
         lat_d, res_d = leg(B.RN_FP64)
@@ -726,19 +750,6 @@ def backbone_bench(args, B, I, np):
                "gpu_ms": round(1e3 * min(walls), 3), "oracle_s": round(t_cpu, 3),
                "gpu_nodes_per_s": round(net.n / min(walls)), "speedup_vs_oracle": round(t_cpu / min(walls), 1),
                "mask_equals_oracle": same}
-        if "RRN" in label:
-            M = m.cpu().numpy()
-            dangling = M == 3
-            gp = [np.array(a, copy=True) for a in net.g]
-            for k in range(net.dim):
-                gp[k][dangling] = 0.0
-                gp[k][np.roll(dangling, -1, axis=net.dim - 1 - k)] = 0.0
-            pruned = I.Network(net.dim, net.nx, net.ny, net.nz, gp, net.axis)
-            for name, n_ in (("full", net), ("backbone_only", pruned)):
-                t = time.perf_counter()
-                r, _, _ = B.solve_network(ctx, n_, B.RN_MIXED, args.tol)
-                row[f"solve_{name}"] = {"K": r.K, "iters": int(r.iters), "converged": bool(r.converged),
-                                        "s": round(time.perf_counter() - t, 3)}
         rows[label] = row
         total_n += net.n
         total_t += min(walls)
@@ -746,11 +757,38 @@ def backbone_bench(args, B, I, np):
               f"live {nl} backbone {nb}, equal {same}", file=sys.stderr, flush=True)
         del gd, m
         torch.cuda.empty_cache()
+    # the RRN toward p_c (Sec. VI, Fig. 7's networks): mixed solves of the whole live set against
+    # RN_OPT_BACKBONE (its backbone pass included), wall time from the call to the result
+    study = {}
+    for p in (0.7, 0.6, 0.55, 0.52):
+        net = I.iid_network(2, 2048, 2048, 1, sigma=0.0, occupancy=p, index=700 + int(100 * p))
+        gd = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in net.g]
+        pr = B.problem(dim=2, nx=net.nx, ny=net.ny, g=gd)
+        row = {}
+        for name, bb in (("live_set", False), ("backbone", True)):
+            best = None
+            for it in range(2):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = ctx.solve(pr, B.opts(B.RN_MIXED, args.tol, backbone=bb))
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                best = dt if best is None else min(best, dt)
+            row[name] = {"s": round(best, 4), "iters": int(r.iters), "K": r.K, "converged": bool(r.converged),
+                         "n_live": int(r.n_live), "n_backbone": int(r.n_backbone)}
+        row["speedup"] = round(row["live_set"]["s"] / row["backbone"]["s"], 3)
+        row["K_rel_diff"] = abs(row["backbone"]["K"] / row["live_set"]["K"] - 1.0) if row["live_set"]["K"] else 0.0
+        study[f"p={p}"] = row
+        print(f"[bench] RRN 2048^2 p={p}: live set {row['live_set']['iters']} iters {row['live_set']['s']:.3f} s, "
+              f"backbone {row['backbone']['iters']} iters {row['backbone']['s']:.3f} s", file=sys.stderr, flush=True)
+        del gd
+        torch.cuda.empty_cache()
     ctx.close()
     out = _contract(args, total_n / total_t, "nodes/s", total_t, args.steps,
                     {"workload": MULTI["backbone"], "inputs": "bonds resident in HBM"}, dtype="int32")
     out["metric"] = "backbone nodes/s (connectivity mask + biconnected block of the inlet-outlet edge)"
     out["cases"] = rows
+    out["rrn_toward_pc"] = study
     return out
 
 

@@ -85,6 +85,15 @@ extern "C" {
                               iterations. rn_solve and rn_solve_batch only (rn_submit: RN_EINVAL).
                               mask_out receives rn_build_backbone's mask; rn_result.n_live counts
                               the whole live set and n_backbone the backbone. */
+#define RN_OPT_COMPACT 2   /* run the CG on a list of the nodes that take part (the live set, or the
+                              backbone with RN_OPT_BACKBONE), each with its neighbours' list
+                              indices, instead of sweeping the whole lattice: fewer bytes per
+                              iteration when few nodes take part (near the percolation threshold).
+                              The same method and stopping rule, so results agree with the lattice
+                              path within the tolerance, not bit for bit. rn_solve and
+                              rn_solve_batch only (rn_submit: RN_EINVAL); each such solve runs on
+                              its own, before the rest of a batch. rn_result.passes counts the
+                              rounds launched (two launches each). */
 
 /* rn_problem.mem */
 #define RN_MEM_HOST 0
@@ -126,7 +135,7 @@ typedef struct {
                            recurrence then continues from the FP64 residual (reliable update).
                            Ignored by RN_FP64. Must lie in [0, 1). */
     int32_t x0;         /* RN_X0_LINEAR (default) or RN_X0_ZERO */
-    int32_t flags;      /* 0 (default) or RN_OPT_BACKBONE; other bits: RN_EINVAL */
+    int32_t flags;      /* 0 (default), RN_OPT_BACKBONE, RN_OPT_COMPACT or both; other bits: RN_EINVAL */
 } rn_opts;
 
 /* Outcome of one solve. */

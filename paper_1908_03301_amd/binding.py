@@ -24,6 +24,7 @@ RN_X0_LINEAR, RN_X0_ZERO = 0, 1
 RN_MEM_HOST, RN_MEM_DEVICE = 0, 1
 RN_PERIODIC = 1
 RN_OPT_BACKBONE = 1
+RN_OPT_COMPACT = 2
 RN_PATH_2D_FULL, RN_PATH_2D_SMALL, RN_PATH_3D = 0, 1, 2
 
 EXPORTED = ["rn_version", "rn_strerror", "rn_opts_default", "rn_create", "rn_destroy", "rn_set_stream",
@@ -146,12 +147,12 @@ def strerror(code: int) -> str:
 
 
 def opts(precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000, delta: float = 0.0,
-         precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR, backbone: bool = False) -> rn_opts:
+         precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR, backbone: bool = False, compact: bool = False) -> rn_opts:
     o = rn_opts()
     lib().rn_opts_default(C.byref(o))
     o.precision, o.tol, o.max_iter, o.delta = int(precision), float(tol), int(max_iter), float(delta)
     o.precond, o.x0 = int(precond), int(x0)
-    o.flags = RN_OPT_BACKBONE if backbone else 0
+    o.flags = (RN_OPT_BACKBONE if backbone else 0) | (RN_OPT_COMPACT if compact else 0)
     return o
 
 
@@ -474,10 +475,10 @@ def rn_solve(ctx: Context, prob: Problem, o: Optional[rn_opts] = None) -> rn_res
 
 def solve_network(ctx: Context, net, precision: int = RN_FP64, tol: float = 1e-8, max_iter: int = 10_000_000,
                   want_pressure: bool = False, want_mask: bool = False, delta: float = 0.0,
-                  precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR, backbone: bool = False):
+                  precond: int = RN_JACOBI, x0: int = RN_X0_LINEAR, backbone: bool = False, compact: bool = False):
     """Host-memory convenience: returns (rn_result, pressure or None, mask or None)."""
     P = np.zeros(net.shape, dtype=np.float64) if want_pressure else None
     M = np.zeros(net.shape, dtype=np.uint8) if want_mask else None
     pr = problem(net, p_out=P, mask_out=M)
-    res = ctx.solve(pr, opts(precision, tol, max_iter, delta, precond, x0, backbone))
+    res = ctx.solve(pr, opts(precision, tol, max_iter, delta, precond, x0, backbone, compact))
     return res, P, M

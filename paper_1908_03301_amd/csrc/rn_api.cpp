@@ -378,7 +378,7 @@ static int backbone_prepare(rn_ctx *ctx, const rn_problem *p, BackbonePrep *b)
     if (n_axis >= 3 && launch_backbone(lat, gc, b->mask, tr + a256(8 * nn), cnt + 2, (int *)ctx->h_small, nullptr,
                                        st) != hipSuccess)
         return fail(RN_EDEVICE);
-    if (launch_backbone_prune(lat, g, b->mask, b->uf, b->att, st) != hipSuccess) return fail(RN_EDEVICE);
+    if (launch_backbone_prune(lat, gc, g, b->mask, b->uf, b->att, st) != hipSuccess) return fail(RN_EDEVICE);
     if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return fail(RN_EDEVICE);
@@ -411,6 +411,193 @@ static int backbone_finish(rn_ctx *ctx, const rn_problem *p, BackbonePrep *b, rn
     return RN_OK;
 }
 
+// ------------------------------------------------------------------ compact solves
+// RN_OPT_COMPACT: the CG runs on the list of the nodes that take part (the
+// live set, or the backbone with RN_OPT_BACKBONE) through neighbour slots, on
+// the caller's thread, outside the engine. Returns RN_OK with *done = false
+// when nothing takes part (the engine then handles the network: direct
+// inlet-outlet bonds, dead pressures). Caller holds call_mu, device current.
+static int compact_solve(rn_ctx *ctx, const rn_problem *p, const rn_opts *o, rn_result *out, bool *done)
+{
+    *done = false;
+    const double t0 = now_s();
+    const int64_t n = p->nx * p->ny * p->nz;
+    if (n + 2 > (int64_t)INT32_MAX) return RN_EINVAL;
+    const size_t nn = (size_t)n;
+    const bool backbone = (o->flags & RN_OPT_BACKBONE) != 0;
+    const bool f32 = o->precision == RN_MIXED;
+    const size_t s = f32 ? 4 : 8;
+    const int slots = 2 * p->dim;
+    const int nb = compact_blocks(n);
+    hipStream_t st = ctx->stream;
+    const hipMemcpyKind kind = p->mem == RN_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    // lattice-side buffers: bonds (host input), mask, field, the pieces of
+    // dangling nodes, counters and index scans; then the transient arrays of
+    // the mask and the backbone
+    const bool copy_g = p->mem == RN_MEM_HOST;
+    const size_t off_g = 0, off_mask = off_g + a256(copy_g ? 8 * (size_t)p->dim * nn : 0),
+                 off_P = off_mask + a256(nn), off_uf = off_P + a256(8 * nn),
+                 off_att = off_uf + a256(backbone ? 4 * nn : 0), off_cmap = off_att + a256(backbone ? 4 * nn : 0),
+                 off_cnt = off_cmap + a256(4 * nn), off_scan = off_cnt + 256,
+                 lat_bytes = off_scan + a256(4 * (2 * (size_t)nb + 1));
+    hipError_t he;
+    char *lb = (char *)ctx->pool.alloc(lat_bytes, &he);
+    if (!lb) return RN_ENOMEM;
+    char *tr = (char *)ctx->pool.alloc(a256(8 * nn) + (backbone ? backbone_scratch_bytes(n) : 0), &he);
+    char *cb = nullptr;
+    auto finish = [&](int r) {
+        (void)hipStreamSynchronize(st);
+        if (tr) ctx->pool.free(tr);
+        if (cb) ctx->pool.free(cb);
+        ctx->pool.free(lb);
+        return r;
+    };
+    if (!tr) return finish(RN_ENOMEM);
+    const double *g[3] = {nullptr, nullptr, nullptr};
+    for (int k = 0; k < p->dim; ++k) {
+        if (copy_g) {
+            double *dst = (double *)(lb + off_g) + (size_t)k * nn;
+            if (hipMemcpyAsync(dst, p->g[k], 8 * nn, hipMemcpyHostToDevice, st) != hipSuccess) return finish(RN_EDEVICE);
+            g[k] = dst;
+        } else {
+            g[k] = p->g[k];
+        }
+    }
+    uint8_t *mask = (uint8_t *)(lb + off_mask);
+    double *Pl = (double *)(lb + off_P);
+    int *uf = (int *)(lb + off_uf), *att = (int *)(lb + off_att), *cmap = (int *)(lb + off_cmap);
+    unsigned long long *cnt = (unsigned long long *)(lb + off_cnt);
+    int *counts = (int *)(lb + off_scan), *offsets = counts + nb;
+    unsigned long long *hc = ctx->h_small;
+    const Lat lat = make_lat(p);
+    if (launch_clear_u64(cnt, 4, st) != hipSuccess) return finish(RN_EDEVICE);
+    if (!copy_g) {
+        if (launch_validate(lat, g, cnt + 1, st) != hipSuccess) return finish(RN_EDEVICE);
+        if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return finish(RN_EDEVICE);
+        if (hc[1] != 0) return finish(RN_EINVAL);
+    }
+    if (launch_mask(lat, g, (int *)tr, (unsigned *)(tr + 4 * nn), mask, Pl, cnt, o->x0 == RN_X0_LINEAR, st) !=
+        hipSuccess)
+        return finish(RN_EDEVICE);
+    const int n_axis = p->axis == 0 ? (int)p->nx : (p->axis == 1 ? (int)p->ny : (int)p->nz);
+    if (backbone && n_axis >= 3) {
+        if (launch_backbone(lat, g, mask, tr + a256(8 * nn), cnt + 2, (int *)ctx->h_small, nullptr, st) != hipSuccess)
+            return finish(RN_EDEVICE);
+        if (launch_backbone_prune(lat, g, nullptr, mask, uf, att, st) != hipSuccess) return finish(RN_EDEVICE);
+    }
+    if (launch_compact_index(mask, n, backbone ? 11 : 3, counts, offsets, (int *)tr, cmap, st) != hipSuccess)
+        return finish(RN_EDEVICE);
+    int mh = 0;
+    if (hipMemcpyAsync(hc, cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipMemcpyAsync(&mh, offsets + nb, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return finish(RN_EDEVICE);
+    const int64_t n_live = (int64_t)hc[0], n_bb = backbone ? (int64_t)hc[2] : 0;
+    const int m = mh;
+    if (m == 0) return finish(RN_OK);           // nothing takes part: the engine's path
+    // member-side buffers (the member list is moved out of the transient area first)
+    int grid = (int)std::min<int64_t>(((int64_t)m + kBlock - 1) / kBlock, 4096);
+    grid = (grid + 7) & ~7;
+    int groups = 1;
+    while (groups < kGroupsMax && groups * 2 * 64 <= grid) groups *= 2;
+    const size_t off_idx = 0, off_nbr = a256(4 * (size_t)m), off_gT = off_nbr + a256(4 * (size_t)slots * m),
+                 off_g64 = off_gT + a256(s * slots * m), off_d = off_g64 + a256(8 * (size_t)slots * m),
+                 off_P0 = off_d + a256(s * m), off_P1 = off_P0 + a256(8 * (size_t)m),
+                 off_z = off_P1 + a256(8 * (size_t)m), off_u = off_z + a256(s * m), off_p = off_u + a256(s * m),
+                 off_part = off_p + a256(s * m), off_tk = off_part + a256(8 * kRed * (size_t)grid),
+                 off_sc = off_tk + a256(ticket_bytes(groups)), cbytes = off_sc + a256(sizeof(Scalars));
+    cb = (char *)ctx->pool.alloc(cbytes, &he);
+    if (!cb) return finish(RN_ENOMEM);
+    int *idx = (int *)(cb + off_idx);
+    if (hipMemcpyAsync(idx, tr, 4 * (size_t)m, hipMemcpyDeviceToDevice, st) != hipSuccess) return finish(RN_EDEVICE);
+    Scalars *ds = (Scalars *)(cb + off_sc);
+    static_assert(sizeof(Scalars) <= 32 * sizeof(unsigned long long), "control block staged in h_small");
+    Scalars &init = *(Scalars *)ctx->h_small;   // pinned; read back into the same words later, in stream order
+    std::memset(&init, 0, sizeof(init));
+    init.mode = MODE_REFRESH;
+    init.first = 1;
+    init.fp32 = f32;
+    init.max_iter = o->max_iter;
+    init.sigma = init.sigma_next = 1.0;
+    init.tol = o->tol;
+    init.delta = f32 ? (o->delta > 0.0 ? o->delta : 0.1) : 0.0;
+    init.kappa = init.bhat = 1.0;
+    init.last_check = INFINITY;
+    if (hipMemcpyAsync(ds, &init, sizeof(init), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemsetAsync(cb + off_tk, 0, ticket_bytes(groups), st) != hipSuccess)
+        return finish(RN_EDEVICE);
+    auto run = [&](auto zero) -> int {
+        using T = decltype(zero);
+        CompactArgs<T> a;
+        a.m = m;
+        a.slots = slots;
+        a.grid = grid;
+        a.groups = groups;
+        a.jacobi = o->precond == RN_JACOBI ? 1 : 0;
+        a.nbr = (const int *)(cb + off_nbr);
+        a.gT = (const T *)(cb + off_gT);
+        a.g64 = (const double *)(cb + off_g64);
+        a.d = (const T *)(cb + off_d);
+        a.P[0] = (double *)(cb + off_P0);
+        a.P[1] = (double *)(cb + off_P1);
+        a.z = (T *)(cb + off_z);
+        a.u = (T *)(cb + off_u);
+        a.p = (T *)(cb + off_p);
+        a.partials = (double *)(cb + off_part);
+        a.tickets = (unsigned *)(cb + off_tk);
+        if (launch_compact_tables<T>(lat, g, idx, cmap, m, (int *)a.nbr, (T *)a.gT, (double *)a.g64, (T *)a.d, Pl,
+                                     a.P[0], a.z, a.u, a.p, st) != hipSuccess)
+            return RN_EDEVICE;
+        const double tl = now_s();
+        int64_t rounds = 0;
+        int chunk = 16;
+        Scalars *hs = (Scalars *)ctx->h_small;
+        while (true) {
+            for (int r = 0; r < chunk; ++r)
+                if (launch_compact_round<T>(a, ds, st) != hipSuccess) return RN_EDEVICE;
+            rounds += chunk;
+            if (hipMemcpyAsync(hs, ds, sizeof(Scalars), hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return RN_EDEVICE;
+            if (hs->mode == MODE_DONE) break;
+            chunk = std::min(chunk * 2, 256);
+        }
+        const Scalars h = *hs;
+        std::memset(out, 0, sizeof(*out));
+        out->status = h.status;
+        out->converged = h.converged;
+        out->Q_in = h.Q_in;
+        out->Q_out = h.Q_out;
+        out->G = h.Q_in - h.xr;
+        out->K = out->G * (double)(n_axis - 1) / cross_section(p);
+        out->rel_resid = h.rel_resid;
+        out->iters = h.iters;
+        out->refreshes = h.refreshes;
+        out->n_live = n_live;
+        out->n_backbone = n_bb;
+        out->passes = rounds;
+        if (out->status == 0 && !out->converged) out->status = RN_ENOCONV;
+        // outputs: the members' field into the lattice field, the dangling
+        // ends' pressures from their backbone nodes, then the caller's buffers
+        if (p->p_out) {
+            if (launch_compact_scatter(idx, m, a.P[h.refreshes & 1], Pl, st) != hipSuccess) return RN_EDEVICE;
+            if (backbone && n_axis >= 3 && launch_backbone_fill(lat, mask, uf, att, Pl, st) != hipSuccess)
+                return RN_EDEVICE;
+            if (hipMemcpyAsync(p->p_out, Pl, 8 * nn, kind, st) != hipSuccess) return RN_EDEVICE;
+        }
+        if (p->mask_out && hipMemcpyAsync(p->mask_out, mask, nn, kind, st) != hipSuccess) return RN_EDEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) return RN_EDEVICE;
+        out->t_loop_s = now_s() - tl;
+        out->t_total_s = now_s() - t0;
+        return RN_OK;
+    };
+    const int r = f32 ? run(0.0f) : run(0.0);
+    if (r == RN_OK) *done = true;
+    return finish(r);
+}
+
 int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opts *opts, int32_t n_opts,
                rn_result *out)
 {
@@ -418,9 +605,24 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
     if (!(n_opts == 0 || n_opts == 1 || n_opts == count)) return RN_EINVAL;
     if (n_opts > 0 && !opts) return RN_EINVAL;
     auto opts_of = [&](int i) { return n_opts == 0 ? nullptr : (n_opts == 1 ? opts : opts + i); };
-    // solves on the backbone: check, then prune their bonds before the engine sees them
+    // solves with options the engine does not take: check them all first
+    std::vector<char> flagged((size_t)count, 0);
+    bool any = false;
+    for (int i = 0; i < count; ++i) {
+        const rn_opts *o = opts_of(i);
+        if (!o || !(o->flags & (RN_OPT_BACKBONE | RN_OPT_COMPACT))) continue;
+        int st = check_shape(probs + i);
+        if (!st) st = check_opts(o);
+        if (!st && probs[i].mem == RN_MEM_HOST && !host_values_ok(probs + i)) st = RN_EINVAL;
+        if (!st && ctx->server) st = RN_EINVAL;      // the server owns the stream
+        if (st) return st;
+        flagged[(size_t)i] = 1;
+        any = true;
+    }
+    // compact solves run here, one by one; solves on the backbone have their
+    // bonds pruned before the engine sees them
     std::vector<BackbonePrep> bb((size_t)count);
-    std::vector<char> on_bb((size_t)count, 0);
+    std::vector<char> on_bb((size_t)count, 0), done((size_t)count, 0);
     std::vector<rn_problem> eff(probs, probs + count);
     auto free_bb = [&]() {
         for (BackbonePrep &b : bb)
@@ -429,34 +631,40 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
                 b.aux = nullptr;
             }
     };
-    bool any_bb = false;
-    for (int i = 0; i < count; ++i) {
-        const rn_opts *o = opts_of(i);
-        if (!o || !(o->flags & RN_OPT_BACKBONE)) continue;
-        int st = check_shape(probs + i);
-        if (!st) st = check_opts(o);
-        if (!st && probs[i].mem == RN_MEM_HOST && !host_values_ok(probs + i)) st = RN_EINVAL;
-        if (!st && ctx->server) st = RN_EINVAL;      // the server owns the stream
-        if (st) return st;
-        on_bb[(size_t)i] = 1;
-        any_bb = true;
-    }
-    if (any_bb) {
+    if (any) {
         std::lock_guard<std::mutex> lk(ctx->call_mu);
         if (ctx->server) return RN_EINVAL;
         if (hipSetDevice(ctx->device) != hipSuccess) return RN_EDEVICE;
         for (int i = 0; i < count; ++i) {
-            if (!on_bb[(size_t)i]) continue;
-            const int st = backbone_prepare(ctx, probs + i, &bb[(size_t)i]);
-            if (st) {
-                free_bb();
-                return st;
+            if (!flagged[(size_t)i]) continue;
+            const rn_opts *o = opts_of(i);
+            if (o->flags & RN_OPT_COMPACT) {
+                bool fin = false;
+                const int st = compact_solve(ctx, probs + i, o, out + i, &fin);
+                if (st) {
+                    free_bb();
+                    return st;
+                }
+                if (fin) {
+                    done[(size_t)i] = 1;
+                    continue;
+                }
             }
-            eff[(size_t)i] = bb[(size_t)i].q;
+            if (o->flags & RN_OPT_BACKBONE) {
+                const int st = backbone_prepare(ctx, probs + i, &bb[(size_t)i]);
+                if (st) {
+                    free_bb();
+                    return st;
+                }
+                eff[(size_t)i] = bb[(size_t)i].q;
+                on_bb[(size_t)i] = 1;
+            }
         }
     }
     std::vector<Net *> nets((size_t)count, nullptr);
+    std::vector<Net *> live;
     for (int i = 0; i < count; ++i) {
+        if (done[(size_t)i]) continue;
         int st = make_net(ctx, &eff[(size_t)i], opts_of(i), &nets[i]);
         if (st) {
             for (Net *n : nets)
@@ -464,42 +672,53 @@ int solve_many(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn_opt
             free_bb();
             return st;
         }
+        live.push_back(nets[i]);
     }
     Sched *S = sched_of(ctx);
     int r = RN_OK;
-    if (ctx->server) {
-        // the server thread drives: hand the networks over and wait for them
-        {
-            CallLock cl(ctx);
-            for (Net *n : nets) S->waiting.push_back(n);
-        }
-        ctx->server->cv.notify_all();
-        while (true) {
-            std::this_thread::sleep_for(std::chrono::microseconds(200));
-            CallLock cl(ctx);
-            bool all_done = true;
-            for (Net *n : nets) all_done = all_done && n->phase == NET_DONE;
-            if (all_done) break;
-        }
-    } else {
-        std::lock_guard<std::mutex> lk(ctx->call_mu);
-        if (hipSetDevice(ctx->device) != hipSuccess) return RN_EDEVICE;
-        for (Net *n : nets) S->waiting.push_back(n);
-        r = drive_until(ctx, S, nets);
-        if (r) {
-            fail_all(ctx, S, r);
-            (void)hipStreamSynchronize(ctx->stream);
-            (void)hipStreamSynchronize(ctx->side);
+    if (!live.empty()) {
+        if (ctx->server) {
+            // the server thread drives: hand the networks over and wait for them
+            {
+                CallLock cl(ctx);
+                for (Net *n : live) S->waiting.push_back(n);
+            }
+            ctx->server->cv.notify_all();
+            while (true) {
+                std::this_thread::sleep_for(std::chrono::microseconds(200));
+                CallLock cl(ctx);
+                bool all_done = true;
+                for (Net *n : live) all_done = all_done && n->phase == NET_DONE;
+                if (all_done) break;
+            }
+        } else {
+            std::lock_guard<std::mutex> lk(ctx->call_mu);
+            if (hipSetDevice(ctx->device) != hipSuccess) {
+                for (Net *n : live) release_net(n);
+                free_bb();
+                return RN_EDEVICE;
+            }
+            for (Net *n : live) S->waiting.push_back(n);
+            r = drive_until(ctx, S, live);
+            if (r) {
+                fail_all(ctx, S, r);
+                (void)hipStreamSynchronize(ctx->stream);
+                (void)hipStreamSynchronize(ctx->side);
+            }
         }
     }
     int first = RN_OK;
     for (int i = 0; i < count; ++i) {
+        if (done[(size_t)i]) {
+            if (out[i].status != RN_OK && first == RN_OK) first = out[i].status;
+            continue;
+        }
         if (!r) out[i] = nets[i]->res;
         if (nets[i]->status != RN_OK && first == RN_OK) first = nets[i]->status;
         if (nets[i]->base) ctx->pool.free(nets[i]->base);
         release_net(nets[i]);
     }
-    if (any_bb && !r) {
+    if (any && !r) {
         // outputs of the solves on the backbone (those that ran: RN_OK or RN_ENOCONV)
         std::lock_guard<std::mutex> lk(ctx->call_mu);
         for (int i = 0; i < count && !r; ++i)
@@ -714,6 +933,14 @@ size_t rn_footprint(const rn_problem *p, const rn_opts *o)
     rn_opts d;
     rn_opts_default(&d);
     size_t bytes = make_layout(p, o ? o : &d).total;
+    if (o && (o->flags & RN_OPT_COMPACT)) {
+        // the lattice side (bonds, mask, field, maps, transient arrays of the
+        // mask and the backbone) and the member side with every node a member
+        const size_t n = (size_t)(p->nx * p->ny * p->nz), s = o->precision == RN_MIXED ? 4 : 8;
+        const size_t slots = 2 * (size_t)p->dim;
+        return 8 * (size_t)p->dim * n + 25 * n + 8 * n + backbone_transient_bytes(p) +
+               n * (4 + slots * (12 + s) + 4 * s + 16) + (1 << 20);
+    }
     if (o && (o->flags & RN_OPT_BACKBONE))   // the pruned copy and its maps, plus the larger of the
         bytes += backbone_aux_bytes(p) +      // backbone's transient arrays and the solve itself
                  (backbone_transient_bytes(p) > bytes ? backbone_transient_bytes(p) - bytes : 0);
@@ -932,7 +1159,7 @@ int rn_solve_batch(rn_ctx *ctx, int32_t count, const rn_problem *probs, const rn
 int rn_submit(rn_ctx *ctx, const rn_problem *p, const rn_opts *opts, uint64_t *ticket_out)
 {
     if (!ctx || !ticket_out) return RN_EINVAL;
-    if (opts && (opts->flags & RN_OPT_BACKBONE)) return RN_EINVAL;   // rn_solve / rn_solve_batch only
+    if (opts && (opts->flags & (RN_OPT_BACKBONE | RN_OPT_COMPACT))) return RN_EINVAL;   // rn_solve(_batch) only
     Net *net = nullptr;
     int st = make_net(ctx, p, opts, &net);
     if (st) return st;

@@ -602,16 +602,15 @@ hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask
     return hipGetLastError();
 }
 
-hipError_t launch_backbone_prune(const Lat &L, double *const g[3], const uint8_t *mask, int *uf, int *att,
-                                 hipStream_t st)
+hipError_t launch_backbone_prune(const Lat &L, const double *const g[3], double *const gw[3], const uint8_t *mask,
+                                 int *uf, int *att, hipStream_t st)
 {
-    const double *gc[3] = {g[0], g[1], L.dim == 3 ? g[2] : nullptr};
-    const BbGraph G = graph_of(L, gc, mask);
+    const BbGraph G = graph_of(L, g, mask);
     const int gr = grid_of(L.n);
     bb_iota<<<gr, kBbBlock, 0, st>>>(uf, (int)L.n);
     bb_piece_union<<<gr, kBbBlock, 0, st>>>(G, uf, att);
     bb_piece_attach<<<gr, kBbBlock, 0, st>>>(G, uf, att);
-    bb_prune<<<gr, kBbBlock, 0, st>>>(G, g[0], g[1], L.dim == 3 ? g[2] : nullptr);
+    if (gw) bb_prune<<<gr, kBbBlock, 0, st>>>(G, gw[0], gw[1], L.dim == 3 ? gw[2] : nullptr);
     return hipGetLastError();
 }
 

@@ -132,6 +132,35 @@ hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st);
 // g[i] in [1, 2) from a hash of i and salt (the networks of the launch-shape trials)
 hipError_t launch_fill_trial(double *g, int64_t n, uint32_t salt, hipStream_t st);
 
+// Compact (gather) path: the m nodes that take part, in lattice order, with
+// 2 dim neighbour slots each (see rn_kernels.hip).
+template <typename T>
+struct CompactArgs {
+    int m, slots, grid, groups, jacobi;
+    const int *nbr;              // [slots][m]: list index, -2 inlet face, -3 outlet face, -1 none
+    const T *gT;                 // [slots][m] inner-precision bonds (0 where none)
+    const double *g64;           // [slots][m]
+    const T *d;                  // [m] inner diagonal: the sum of the node's gT
+    double *P[2];                // FP64 field; a refresh reads P[refreshes & 1] and writes the other
+    T *z, *u, *p;                // [m]
+    double *partials;            // [grid][kRed]
+    unsigned *tickets;           // groups + 1 counters, kTicketStride bytes apart
+};
+int compact_blocks(int64_t n);   // blocks of the member count / placement launches
+// idx[c]: lattice index of member c (mask == want), in lattice order; cmap[i]:
+// member index of lattice node i or -1; counts: compact_blocks(n) ints;
+// offsets: compact_blocks(n) + 1 ints, offsets[last] = m.
+hipError_t launch_compact_index(const uint8_t *mask, int64_t n, uint8_t want, int *counts, int *offsets, int *idx,
+                                int *cmap, hipStream_t st);
+template <typename T>
+hipError_t launch_compact_tables(const Lat &L, const double *const g[3], const int *idx, const int *cmap, int m,
+                                 int *nbr, T *gT, double *g64, T *d, const double *P0, double *P, T *z, T *u, T *p,
+                                 hipStream_t st);
+// one CG or refresh round (the control block's mode decides): two launches
+template <typename T>
+hipError_t launch_compact_round(const CompactArgs<T> &a, Scalars *s, hipStream_t st);
+hipError_t launch_compact_scatter(const int *idx, int m, const double *P, double *Pl, hipStream_t st);
+
 // Backbone (rn_backbone.hip): with `mask` the connectivity mask of the
 // lattice, set bit 3 on every interior node of the backbone and add their
 // number to *n_backbone (a device counter). `scratch` holds
@@ -146,10 +175,10 @@ hipError_t launch_backbone(const Lat &L, const double *const g[3], uint8_t *mask
                            unsigned long long *n_backbone, int *h_stage, int *depth_out, hipStream_t st);
 // With `mask` from launch_backbone (backbone 11, dangling 3): find the pieces
 // of dangling nodes (uf, n ints) and the backbone node each hangs from (att,
-// n ints, at the piece's root), then zero in place every bond of g (device,
-// writable) with a dangling end.
-hipError_t launch_backbone_prune(const Lat &L, double *const g[3], const uint8_t *mask, int *uf, int *att,
-                                 hipStream_t st);
+// n ints, at the piece's root) from the bonds g, then, when gw (a writable
+// device copy of g) is given, zero in place every bond of gw with a dangling end.
+hipError_t launch_backbone_prune(const Lat &L, const double *const g[3], double *const gw[3], const uint8_t *mask,
+                                 int *uf, int *att, hipStream_t st);
 // After the solve of the pruned network: every dangling node takes the
 // pressure of the backbone node its piece hangs from.
 hipError_t launch_backbone_fill(const Lat &L, const uint8_t *mask, int *uf, const int *att, double *P,

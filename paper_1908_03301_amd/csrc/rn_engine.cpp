@@ -69,7 +69,7 @@ int check_opts(const rn_opts *o)
     if (!(o->delta >= 0.0) || o->delta >= 1.0) return RN_EINVAL;
     if (o->precond != RN_JACOBI && o->precond != RN_NONE) return RN_EINVAL;
     if (o->x0 != RN_X0_LINEAR && o->x0 != RN_X0_ZERO) return RN_EINVAL;
-    if (o->flags & ~RN_OPT_BACKBONE) return RN_EINVAL;
+    if (o->flags & ~(RN_OPT_BACKBONE | RN_OPT_COMPACT)) return RN_EINVAL;
     return RN_OK;
 }
 

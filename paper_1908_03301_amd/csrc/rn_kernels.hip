@@ -1637,6 +1637,241 @@ hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- compact (gather) path
+// For networks where few nodes take part (the live set, or the backbone, near
+// the percolation threshold) the lattice sweep moves the bytes of every node.
+// The compact path lists the m nodes that take part, in lattice order, with
+// their 2 dim neighbour slots (the neighbour's list index; -2 / -3 for a bond
+// to the inlet / outlet face; -1 for none), and runs the same CG in two
+// launches per iteration:
+//   A: the FP64 field takes the pending step (P += sigma alpha p), then
+//      z' = z - alpha u and p' = z' + beta p, in place;
+//   B: q = A p' by gathering the neighbours' p', u = M^-1 q, and the four dot
+//      products of the dense pass, reduced by finish_pass (same tickets,
+//      same scalar step). A refresh round runs in B alone (A sees its mode
+//      and does nothing): r = b - A P in FP64 with the pending step added to
+//      every pressure read, as refresh_node does, into the other P buffer.
+// Each pending step is applied in the next A, so at most one is pending.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void compact_pass_a(CompactArgs<T> a, const Scalars *s)
+{
+    if (s->mode != MODE_CG) return;
+    const T alpha = (T)s->alpha, beta = (T)s->beta;
+    const double sa = s->sigma * s->alpha;
+    double *P = a.P[s->refreshes & 1];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.m; c += gridDim.x * blockDim.x) {
+        const T p0 = a.p[c];
+        if (sa != 0.0) P[c] = fma(sa, (double)p0, P[c]);
+        const T zc = a.z[c] - alpha * a.u[c];
+        a.z[c] = zc;
+        a.p[c] = zc + beta * p0;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void compact_pass_b(CompactArgs<T> a, Scalars *s)
+{
+    const int mode = s->mode;
+    if (mode == MODE_DONE) return;
+    const unsigned long long spre = prefetch_scalars(s);
+    double acc[kRed] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool jacobi = a.jacobi != 0;
+    if (mode == MODE_CG) {
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.m; c += gridDim.x * blockDim.x) {
+            const T pc = a.p[c];
+            T q = T(0);
+            for (int e = 0; e < a.slots; ++e) {
+                const int j = a.nbr[(size_t)e * a.m + c];
+                const T g = a.gT[(size_t)e * a.m + c];
+                const T pn = j >= 0 ? a.p[j] : T(0);
+                q += g * (pc - pn);
+            }
+            const T d = a.d[c];
+            const T uv = d > T(0) ? apply_minv(q, d, jacobi) : T(0);
+            a.u[c] = uv;
+            const double dq = (double)q, dz = (double)a.z[c];
+            acc[0] += (double)pc * dq;
+            acc[1] += dz * dq;
+            acc[2] += dq * (double)uv;
+            acc[3] += (double)(jacobi ? d : T(1)) * dz * dz;
+        }
+    } else {
+        const int m = (int)(s->refreshes & 1);
+        const double *Ps = a.P[m];
+        double *Pd = a.P[m ^ 1];
+        const double sa = s->sigma * s->alpha, sigma_next = s->sigma_next;
+        const bool bonly = s->first == 1;
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.m; c += gridDim.x * blockDim.x) {
+            const double Pi = Ps[c];
+            const double pi = bonly ? 0.0 : (sa != 0.0 ? fma(sa, (double)a.p[c], Pi) : Pi);
+            double r64 = 0.0, qin = 0.0, qout = 0.0;
+            for (int e = 0; e < a.slots; ++e) {
+                const int j = a.nbr[(size_t)e * a.m + c];
+                const double g = a.g64[(size_t)e * a.m + c];
+                if (g == 0.0) continue;
+                if (j >= 0) {
+                    const double Pj = Ps[j];
+                    const double pn = bonly ? 0.0 : (sa != 0.0 ? fma(sa, (double)a.p[j], Pj) : Pj);
+                    r64 += g * (pn - pi);
+                } else if (j == -2) {
+                    r64 += g * (1.0 - pi);
+                    qin += g * (1.0 - pi);
+                } else {
+                    r64 += g * (0.0 - pi);
+                    qout += g * pi;
+                }
+            }
+            const T dT = a.d[c];
+            const T rs = (T)(r64 / sigma_next);
+            const T zs = dT > T(0) ? apply_minv(rs, dT, jacobi) : T(0);
+            Pd[c] = bonly ? Pi : pi;
+            a.z[c] = zs;
+            a.u[c] = T(0);
+            acc[0] += r64 * r64;
+            acc[1] += (double)rs * (double)zs;
+            acc[2] += pi * r64;
+            acc[3] += qin;
+            acc[4] += qout;
+        }
+    }
+    finish_pass<0>(acc, a.partials, a.tickets, s, (int)blockIdx.x, a.grid, a.groups, mode, spre);
+}
+
+// Members (mask == want) counted per block of kCmpChunk nodes.
+constexpr int kCmpChunk = 4 * kBlock;
+
+__global__ __launch_bounds__(kBlock) void compact_count(const uint8_t *mask, int64_t n, uint8_t want, int *counts)
+{
+    const int64_t b0 = (int64_t)blockIdx.x * kCmpChunk;
+    int c = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = b0 + (int64_t)k * kBlock + threadIdx.x;
+        if (i < n && mask[i] == want) ++c;
+    }
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, kWave);
+    __shared__ int ws[kBlock / kWave];
+    if ((threadIdx.x & (kWave - 1)) == 0) ws[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += ws[w];
+        counts[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of the block counts in one workgroup; offsets[nb] = total.
+__global__ __launch_bounds__(kBlock) void compact_scan(const int *counts, int nb, int *offsets)
+{
+    __shared__ int ws[kBlock / kWave];
+    __shared__ int carry;
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nb; b0 += kBlock) {
+        const int v = b0 + (int)threadIdx.x < nb ? counts[b0 + threadIdx.x] : 0;
+        int inc = v;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) ws[w] = inc;
+        __syncthreads();
+        int before = carry;
+        for (int ww = 0; ww < w; ++ww) before += ws[ww];
+        if (b0 + (int)threadIdx.x < nb) offsets[b0 + threadIdx.x] = before + inc - v;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry = before + inc;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) offsets[nb] = carry;
+}
+
+// List index of every member (in lattice order) and the lattice -> list map.
+__global__ __launch_bounds__(kBlock) void compact_place(const uint8_t *mask, int64_t n, uint8_t want,
+                                                        const int *offsets, int *idx, int *cmap)
+{
+    __shared__ int ws[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const int64_t b0 = (int64_t)blockIdx.x * kCmpChunk;
+    int base = offsets[blockIdx.x];
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = b0 + (int64_t)k * kBlock + threadIdx.x;
+        const int f = (i < n && mask[i] == want) ? 1 : 0;
+        int inc = f;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) ws[w] = inc;
+        __syncthreads();
+        int before = base;
+        for (int ww = 0; ww < w; ++ww) before += ws[ww];
+        int total = base;
+        for (int ww = 0; ww < kBlock / kWave; ++ww) total += ws[ww];
+        if (i < n) {
+            const int c = before + inc - f;
+            cmap[i] = f ? c : -1;
+            if (f) idx[c] = (int)i;
+        }
+        __syncthreads();
+        base = total;
+    }
+}
+
+// Neighbour slots, bonds, inner diagonal and the state of every member; the
+// initial field from the lattice field P0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void compact_tables(Lat L, const double *g0, const double *g1, const double *g2,
+                                                         const int *idx, const int *cmap, int m, int *nbr, T *gT,
+                                                         double *g64, T *d, const double *P0, double *P, T *z, T *u,
+                                                         T *p)
+{
+    const double *g[3] = {g0, g1, g2};
+    const int n3[3] = {L.nx, L.ny, L.nz};
+    const int64_t st[3] = {1, (int64_t)L.nx, (int64_t)L.nx * L.ny};
+    const int na = n3[L.axis];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m; c += gridDim.x * blockDim.x) {
+        const int64_t i = idx[c];
+        const int cc[3] = {(int)(i % L.nx), (int)((i / L.nx) % L.ny), (int)(i / ((int64_t)L.nx * L.ny))};
+        T gs[6];
+        for (int e = 0; e < 2 * L.dim; ++e) {
+            const int k = e >> 1;
+            const bool up = e & 1, wk = (L.wrap >> k) & 1;
+            int64_t j = -1;
+            double gv = 0.0;
+            if (up) {
+                if (cc[k] + 1 < n3[k]) j = i + st[k];
+                else if (wk) j = i - (int64_t)(n3[k] - 1) * st[k];
+                if (j >= 0) gv = g[k][i];
+            } else {
+                if (cc[k] > 0) j = i - st[k];
+                else if (wk) j = i + (int64_t)(n3[k] - 1) * st[k];
+                if (j >= 0) gv = g[k][j];
+            }
+            int code = -1;
+            if (j >= 0 && gv > 0.0) {
+                const int ca = k == L.axis ? cc[k] + (up ? 1 : -1) : cc[L.axis];
+                if (ca == 0) code = -2;
+                else if (ca == na - 1) code = -3;
+                else code = cmap[j];              // -1: not a member (a bond that carries no current)
+            }
+            if (code == -1) gv = 0.0;
+            nbr[(size_t)e * m + c] = code;
+            g64[(size_t)e * m + c] = gv;
+            gs[e] = (T)gv;
+            gT[(size_t)e * m + c] = gs[e];
+        }
+        d[c] = L.dim == 2 ? diag_sum(gs[0], gs[1], gs[2], gs[3]) : diag_sum(gs[0], gs[1], gs[2], gs[3], gs[4], gs[5]);
+        P[c] = P0[i];
+        z[c] = u[c] = p[c] = T(0);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void compact_scatter(const int *idx, int m, const double *P, double *Pl)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m; c += gridDim.x * blockDim.x) Pl[idx[c]] = P[c];
+}
+
 // ---------------------------------------------------------------- host launchers
 
 static inline int grid_for(int64_t n)
@@ -1764,5 +1999,52 @@ template hipError_t launch_pass<float>(int, const PassArgs<float> *, const uint2
                                        hipStream_t);
 template hipError_t launch_pass<double>(int, const PassArgs<double> *, const uint2 *, Scalars *, int, int, int,
                                         hipStream_t);
+
+
+// ---------------------------------------------------------------- compact launchers
+int compact_blocks(int64_t n) { return (int)((n + kCmpChunk - 1) / kCmpChunk); }
+
+hipError_t launch_compact_index(const uint8_t *mask, int64_t n, uint8_t want, int *counts, int *offsets, int *idx,
+                                int *cmap, hipStream_t st)
+{
+    const int nb = compact_blocks(n);
+    compact_count<<<nb, kBlock, 0, st>>>(mask, n, want, counts);
+    compact_scan<<<1, kBlock, 0, st>>>(counts, nb, offsets);
+    compact_place<<<nb, kBlock, 0, st>>>(mask, n, want, offsets, idx, cmap);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_compact_tables(const Lat &L, const double *const g[3], const int *idx, const int *cmap, int m,
+                                 int *nbr, T *gT, double *g64, T *d, const double *P0, double *P, T *z, T *u, T *p,
+                                 hipStream_t st)
+{
+    compact_tables<T><<<grid_for(m), kBlock, 0, st>>>(L, g[0], g[1], L.dim == 3 ? g[2] : nullptr, idx, cmap, m, nbr,
+                                                      gT, g64, d, P0, P, z, u, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_compact_round(const CompactArgs<T> &a, Scalars *s, hipStream_t st)
+{
+    compact_pass_a<T><<<a.grid, kBlock, 0, st>>>(a, s);
+    compact_pass_b<T><<<a.grid, kBlock, 0, st>>>(a, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_scatter(const int *idx, int m, const double *P, double *Pl, hipStream_t st)
+{
+    compact_scatter<<<grid_for(m), kBlock, 0, st>>>(idx, m, P, Pl);
+    return hipGetLastError();
+}
+
+template hipError_t launch_compact_tables<float>(const Lat &, const double *const[3], const int *, const int *, int,
+                                                 int *, float *, double *, float *, const double *, double *, float *,
+                                                 float *, float *, hipStream_t);
+template hipError_t launch_compact_tables<double>(const Lat &, const double *const[3], const int *, const int *, int,
+                                                  int *, double *, double *, double *, const double *, double *,
+                                                  double *, double *, double *, hipStream_t);
+template hipError_t launch_compact_round<float>(const CompactArgs<float> &, Scalars *, hipStream_t);
+template hipError_t launch_compact_round<double>(const CompactArgs<double> &, Scalars *, hipStream_t);
 
 }  // namespace rn

@@ -78,7 +78,7 @@ int main()
     expect(rn_validate(&p, &bad) == RN_EINVAL, "tol 0");
     bad = o; bad.precision = 5;
     expect(rn_validate(&p, &bad) == RN_EINVAL, "precision 5");
-    bad = o; bad.flags = 2;
+    bad = o; bad.flags = 4;
     expect(rn_validate(&p, &bad) == RN_EINVAL, "unknown option flag");
     bad = o; bad.flags = RN_OPT_BACKBONE;
     expect(rn_validate(&p, &bad) == RN_OK && rn_footprint(&p, &bad) > rn_footprint(&p, &o), "backbone option");

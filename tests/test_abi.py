@@ -112,8 +112,10 @@ def test_opts_precond_and_initial_guess(lib):
     for prec in (B.RN_JACOBI, B.RN_NONE):
         for x0 in (B.RN_X0_LINEAR, B.RN_X0_ZERO):
             assert B.rn_validate(p, B.opts(precond=prec, x0=x0)) == B.RN_OK
-    assert B.rn_validate(p, B.opts(backbone=True)) == B.RN_OK
-    for field, bad in (("precond", 2), ("precond", -1), ("x0", 2), ("x0", -1), ("flags", 2), ("flags", -1)):
+    for bb in (False, True):
+        for cp in (False, True):
+            assert B.rn_validate(p, B.opts(backbone=bb, compact=cp)) == B.RN_OK
+    for field, bad in (("precond", 2), ("precond", -1), ("x0", 2), ("x0", -1), ("flags", 4), ("flags", -1)):
         o = B.opts()
         setattr(o, field, bad)
         assert B.rn_validate(p, o) == B.RN_EINVAL, field

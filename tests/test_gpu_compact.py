@@ -1,0 +1,123 @@
+"""GPU parity of the compact path (RN_OPT_COMPACT) with the oracle (Sec. II, Eqs. 3-4; Sec. VI).
+
+The compact path runs the same preconditioned CG, mixed or FP64, on a list of
+the nodes that take part (the live set, or the backbone with RN_OPT_BACKBONE)
+with neighbour slots, instead of sweeping the lattice. Each solve is held to
+the oracle's solve of the whole network at 1e-13: K within 1e-9 (FP64) /
+1e-7 (mixed), the true residual and the energy of the returned field
+re-evaluated by the oracle, every live pressure within the energy bound, and
+the mask bit for bit. Cases: 2D and 3D, both precisions, periodic sides,
+flow along y and z, diluted near the threshold, device memory, nothing
+spanning and 2 planes on the flow axis (handled by the lattice path), a batch
+that mixes compact and lattice solves (each equal to the same solve alone),
+and the request server's rejection of the flag.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_03301_amd import binding as B
+from paper_1908_03301_amd import inputs as I
+from tests import _pins
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.RN_FP64: 1e-10, B.RN_MIXED: 1e-8}
+KBAR = {B.RN_FP64: 1e-9, B.RN_MIXED: 1e-7}
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def cases():
+    return [
+        ("iid 2D 300x257 p0.55 mixed", I.iid_network(2, 300, 257, 1, occupancy=0.55, index=6100), B.RN_MIXED, False),
+        ("iid 2D 300x257 p0.55 mixed backbone", I.iid_network(2, 300, 257, 1, occupancy=0.55, index=6100),
+         B.RN_MIXED, True),
+        ("fbm 2D 260x300 occ0.6 axis y fp64", I.fbm_network(2, 260, 300, 1, H=0.7, sigma=1.5, occupancy=0.6,
+                                                           index=6101, axis=1), B.RN_FP64, False),
+        ("iid 3D 48x40x36 p0.3 mixed", I.iid_network(3, 48, 40, 36, occupancy=0.3, index=6102), B.RN_MIXED, False),
+        ("iid 3D 48x40x36 p0.3 fp64 backbone", I.iid_network(3, 48, 40, 36, occupancy=0.3, index=6102),
+         B.RN_FP64, True),
+        ("layered 3D 40^3 occ0.3 axis z mixed backbone",
+         I.stratified_network(40, H=0.8, sigma=2.0, occupancy=0.3, index=6103, axis=2), B.RN_MIXED, True),
+        ("periodic 2D 200x150 p0.56 mixed", I.iid_network(2, 200, 150, 1, occupancy=0.56, index=6104,
+                                                          periodic=True), B.RN_MIXED, False),
+        ("periodic 3D 30x2x24 p0.5 fp64 backbone", I.iid_network(3, 30, 2, 24, occupancy=0.5, index=6105,
+                                                                 periodic=True), B.RN_FP64, True),
+        ("uniform 2D 70x50 mixed", I.uniform_network(2, 70, 50, 1, g0=2.0), B.RN_MIXED, False),
+        ("nothing spans 2D p0.3 mixed", I.iid_network(2, 200, 200, 1, occupancy=0.3, index=6106), B.RN_MIXED, False),
+        ("2 planes 2x50 fp64", I.iid_network(2, 2, 50, 1, occupancy=0.9, index=6107), B.RN_FP64, True),
+    ]
+
+
+@pytest.mark.parametrize("label,net,prec,bb", cases(), ids=[c[0] for c in cases()])
+def test_compact_against_oracle(ctx, oracle_mod, label, net, prec, bb):
+    say(f"RN_OPT_COMPACT {label}")
+    r, P, M = B.solve_network(ctx, net, prec, TOL[prec], want_pressure=True, want_mask=True, backbone=bb,
+                              compact=True)
+    r0, _, _ = B.solve_network(ctx, net, prec, TOL[prec], backbone=bb)
+    ref = oracle_mod.solve(net, tol=1e-13)
+    if bb:
+        mref, nl, nb = oracle_mod.backbone(net)
+    else:
+        (mref, nl), nb = oracle_mod.mask_bfs(net), 0
+    say(f"{label}: live {r.n_live} backbone {r.n_backbone} K {r.K:.12g} oracle {ref.K:.12g} "
+        f"iters {r.iters} (lattice path {r0.iters})")
+    np.testing.assert_array_equal(M, mref)
+    assert (r.n_live, r.n_backbone) == (nl, nb)
+    assert r.status == 0 and r.converged
+    if nl == 0:
+        assert r.K == pytest.approx(ref.K, rel=1e-12, abs=1e-300) and r.iters == 0
+        return
+    assert r.K == pytest.approx(ref.K, rel=KBAR[prec])
+    assert r.K == pytest.approx(r0.K, rel=2 * KBAR[prec])
+    c = oracle_mod.check_pressure(net, P)
+    assert c.rel_resid <= 1.01 * TOL[prec]
+    assert r.G == pytest.approx(c.G_E, rel=1e-9)
+    live = (mref.ravel() & 3) == 3
+    R = _pins.face_path_resistance(net).ravel()[live]
+    eps = _pins.pressure_error_bound(R, _pins.energy(net, P), ref.G)
+    err = np.abs(P.ravel()[live] - ref.pressure.ravel()[live])
+    assert np.all(err <= eps), float(np.max(err - eps))
+    # the same method on fewer nodes: iteration counts close to the lattice path's
+    assert abs(r.iters - r0.iters) <= max(8, 0.1 * r0.iters), (r.iters, r0.iters)
+
+
+def test_compact_device_memory_and_mixed_batch(ctx):
+    import torch
+    nets = [I.iid_network(2, 220, 180, 1, occupancy=0.55, index=6140),
+            I.fbm_network(2, 300, 240, 1, H=0.7, sigma=1.5, occupancy=0.6, index=6141),
+            I.iid_network(3, 40, 36, 30, occupancy=0.3, index=6142)]
+    flags = [(True, True), (False, False), (False, True)]      # (backbone, compact)
+    solo = [B.solve_network(ctx, n, B.RN_MIXED, 1e-8, want_pressure=True, want_mask=True, backbone=bb, compact=cp)
+            for n, (bb, cp) in zip(nets, flags)]
+    gs = [[torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in n.g] for n in nets]
+    Ps = [torch.zeros(n.shape, dtype=torch.float64, device="cuda") for n in nets]
+    Ms = [torch.zeros(n.shape, dtype=torch.uint8, device="cuda") for n in nets]
+    probs = [B.problem(dim=n.dim, nx=n.nx, ny=n.ny, nz=n.nz, axis=n.axis, g=g, p_out=P, mask_out=M)
+             for n, g, P, M in zip(nets, gs, Ps, Ms)]
+    res = ctx.solve_batch(probs, [B.opts(B.RN_MIXED, 1e-8, backbone=bb, compact=cp) for bb, cp in flags])
+    for (r0, P0, M0), r, P, M in zip(solo, res, Ps, Ms):
+        for f in ("status", "converged", "K", "G", "Q_in", "Q_out", "iters", "n_live", "n_backbone"):
+            assert getattr(r0, f) == getattr(r, f), f
+        assert P0.tobytes() == P.cpu().numpy().tobytes()
+        np.testing.assert_array_equal(M0, M.cpu().numpy())
+
+
+def test_compact_rejected_by_submit(ctx):
+    net = I.iid_network(2, 64, 64, 1, occupancy=0.6, index=6150)
+    with pytest.raises(B.RNError):
+        ctx.submit(B.problem(net), B.opts(B.RN_MIXED, 1e-8, compact=True))
