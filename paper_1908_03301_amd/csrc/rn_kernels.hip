@@ -1668,7 +1668,9 @@ __global__ __launch_bounds__(kBlock) void compact_pass_a(CompactArgs<T> a, const
     }
 }
 
-template <typename T>
+// SLOTS = 2 dim, a compile-time count so that a node's neighbour indices,
+// bonds and gathered directions are all in flight at once.
+template <typename T, int SLOTS>
 __global__ __launch_bounds__(kBlock) void compact_pass_b(CompactArgs<T> a, Scalars *s)
 {
     const int mode = s->mode;
@@ -1679,13 +1681,18 @@ __global__ __launch_bounds__(kBlock) void compact_pass_b(CompactArgs<T> a, Scala
     if (mode == MODE_CG) {
         for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.m; c += gridDim.x * blockDim.x) {
             const T pc = a.p[c];
-            T q = T(0);
-            for (int e = 0; e < a.slots; ++e) {
-                const int j = a.nbr[(size_t)e * a.m + c];
-                const T g = a.gT[(size_t)e * a.m + c];
-                const T pn = j >= 0 ? a.p[j] : T(0);
-                q += g * (pc - pn);
+            int j[SLOTS];
+            T g[SLOTS], pn[SLOTS];
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) {
+                j[e] = a.nbr[(size_t)e * a.m + c];
+                g[e] = a.gT[(size_t)e * a.m + c];
             }
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) pn[e] = a.p[j[e] >= 0 ? j[e] : c];   // in-bounds address, then select
+            T q = T(0);
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) q += g[e] * (pc - (j[e] >= 0 ? pn[e] : T(0)));
             const T d = a.d[c];
             const T uv = d > T(0) ? apply_minv(q, d, jacobi) : T(0);
             a.u[c] = uv;
@@ -1704,21 +1711,33 @@ __global__ __launch_bounds__(kBlock) void compact_pass_b(CompactArgs<T> a, Scala
         for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < a.m; c += gridDim.x * blockDim.x) {
             const double Pi = Ps[c];
             const double pi = bonly ? 0.0 : (sa != 0.0 ? fma(sa, (double)a.p[c], Pi) : Pi);
+            int j[SLOTS];
+            double g[SLOTS], Pj[SLOTS];
+            T pj[SLOTS];
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) {
+                j[e] = a.nbr[(size_t)e * a.m + c];
+                g[e] = a.g64[(size_t)e * a.m + c];
+            }
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) {
+                const int jj = j[e] >= 0 ? j[e] : c;
+                Pj[e] = Ps[jj];
+                pj[e] = a.p[jj];
+            }
             double r64 = 0.0, qin = 0.0, qout = 0.0;
-            for (int e = 0; e < a.slots; ++e) {
-                const int j = a.nbr[(size_t)e * a.m + c];
-                const double g = a.g64[(size_t)e * a.m + c];
-                if (g == 0.0) continue;
-                if (j >= 0) {
-                    const double Pj = Ps[j];
-                    const double pn = bonly ? 0.0 : (sa != 0.0 ? fma(sa, (double)a.p[j], Pj) : Pj);
-                    r64 += g * (pn - pi);
-                } else if (j == -2) {
-                    r64 += g * (1.0 - pi);
-                    qin += g * (1.0 - pi);
+#pragma unroll
+            for (int e = 0; e < SLOTS; ++e) {
+                if (g[e] == 0.0) continue;
+                if (j[e] >= 0) {
+                    const double pn = bonly ? 0.0 : (sa != 0.0 ? fma(sa, (double)pj[e], Pj[e]) : Pj[e]);
+                    r64 += g[e] * (pn - pi);
+                } else if (j[e] == -2) {
+                    r64 += g[e] * (1.0 - pi);
+                    qin += g[e] * (1.0 - pi);
                 } else {
-                    r64 += g * (0.0 - pi);
-                    qout += g * pi;
+                    r64 += g[e] * (0.0 - pi);
+                    qout += g[e] * pi;
                 }
             }
             const T dT = a.d[c];
@@ -2028,7 +2047,8 @@ template <typename T>
 hipError_t launch_compact_round(const CompactArgs<T> &a, Scalars *s, hipStream_t st)
 {
     compact_pass_a<T><<<a.grid, kBlock, 0, st>>>(a, s);
-    compact_pass_b<T><<<a.grid, kBlock, 0, st>>>(a, s);
+    if (a.slots == 6) compact_pass_b<T, 6><<<a.grid, kBlock, 0, st>>>(a, s);
+    else compact_pass_b<T, 4><<<a.grid, kBlock, 0, st>>>(a, s);
     return hipGetLastError();
 }
 
