@@ -525,6 +525,7 @@ static int compact_solve(rn_ctx *ctx, const rn_problem *p, const rn_opts *o, rn_
     init.delta = f32 ? (o->delta > 0.0 ? o->delta : 0.1) : 0.0;
     init.kappa = init.bhat = 1.0;
     init.last_check = INFINITY;
+    init.kpend = 2;                             // unused here: pass A applies each step in the next round
     if (hipMemcpyAsync(ds, &init, sizeof(init), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemsetAsync(cb + off_tk, 0, ticket_bytes(groups), st) != hipSuccess)
         return finish(RN_EDEVICE);

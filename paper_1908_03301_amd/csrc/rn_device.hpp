@@ -23,14 +23,17 @@ struct Scalars {
     int32_t stop;       // finish after the pending refresh (breakdown path)
     int32_t fp32;       // inner vectors are FP32
     int32_t check;      // the pending refresh is a convergence check
-    int32_t flush;      // the next CG pass adds both pending steps to the FP64 field
+    int32_t flush;      // the next CG pass adds every pending step to the FP64 field
+    int32_t kpend;      // steps a CG pass may leave pending before one adds them all (2 or 4)
+    int32_t npend;      // steps pending after the last pass (a refresh counts one, of size 0)
     int64_t iters;      // CG passes executed
     int64_t refreshes;  // refresh passes executed
     int64_t passes;     // passes that did work
     int64_t max_iter;
     double alpha;       // step of the pending update x += alpha p, z -= alpha u
-    double alpha2;      // step of the update before it, still pending when the last CG
-                        // pass did not touch the FP64 field (else 0)
+    double alpha2;      // steps of the updates before it, newest first, still pending while
+    double alpha3;      // the CG passes after them left the FP64 field alone (else 0)
+    double alpha4;
     double beta;        // p = z + beta p in the next CG pass
     double rho;         // exact r_k.z_k of the stored residual at the last CG pass
     double sigma;       // the stored state (z = D^-1 r, p, u = D^-1 A p) is scaled by 1 / sigma
@@ -47,7 +50,7 @@ struct Scalars {
     double Q_in, Q_out, xr;  // fluxes and x.(b - A x) from the last refresh
     // to 256 bytes: control blocks of different networks share no 128-byte
     // line, so networks placed on different XCDs never write one line
-    uint32_t pad_[10];
+    uint32_t pad_[4];
 };
 
 constexpr int kRed = 5;          // partial sums per workgroup
@@ -67,8 +70,8 @@ constexpr int kBlock = 256;      // threads per workgroup of every kernel here
 constexpr int kWave = 64;
 
 // CG state of one parity: z = D^-1 r and u = D^-1 A p. The direction p has
-// three buffers (PassArgs::pbuf) because a pass may still need the one two
-// passes back.
+// kpend + 1 buffers (PassArgs::pbuf) because a pass may still need the ones
+// of the kpend - 1 passes before.
 template <typename T>
 struct VecSet {
     T *z, *u;
@@ -102,9 +105,11 @@ struct PassArgs {
                                  // exactly on live and face nodes
     const uint8_t *mask;         // mask byte per node (3 = live)
     VecSet<T> src, dst;
-    T *pbuf[3];                  // direction p: the c-th pass of a solve (Scalars::passes = c)
-                                 // writes pbuf[c % 3] and reads pbuf[(c + 2) % 3], and a CG pass
-                                 // that flushes the FP64 field also pbuf[(c + 1) % 3]
+    T *pbuf[5];                  // direction p in npbuf = kpend + 1 buffers: the c-th pass of a
+                                 // solve (Scalars::passes = c) writes pbuf[c % npbuf] and reads
+                                 // pbuf[(c - 1) % npbuf]; a CG pass that flushes the FP64 field
+                                 // also reads the buffers of the older pending steps
+    int npbuf;
     // reduction
     double *partials;            // [grid][kRed]
     unsigned *tickets;           // groups + 1 counters, kTicketStride bytes apart, zero between passes

@@ -302,7 +302,10 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.off_P = take(16 * n);
     L.off_mask = take(n);
     L.off_gT = take((size_t)L.s * L.dim * n);
-    L.off_vec = take((size_t)7 * L.s * n);   // two sets of z, u and three p; labels (8 bytes/node) alias here
+    L.kpend = (L.dim == 2 && L.s == 4) ? 4 : 2;
+    // two sets of z and u and kpend + 1 directions; the labels of the
+    // connectivity kernels (8 bytes per node) alias here
+    L.off_vec = take((size_t)(5 + L.kpend) * L.s * n);
     L.off_part = take((size_t)L.grid * kRed * 8);
     L.off_tk = take(ticket_bytes(L.groups));
     L.off_cnt = take(4 * sizeof(unsigned long long));
@@ -562,7 +565,8 @@ static void fill_args(PassArgs<T> *a2, const Net *net, int first_parity, Scalars
         A.P[1] = A.P[0] + n;
         A.mask = (const uint8_t *)(base + L.off_mask);
         A.src = k == 0 ? s0 : s1;
-        for (int b = 0; b < 3; ++b) A.pbuf[b] = vec + (4 + b) * n;
+        for (int b = 0; b < 5; ++b) A.pbuf[b] = b <= L.kpend ? vec + (4 + b) * n : nullptr;
+        A.npbuf = L.kpend + 1;
         A.dst = k == 0 ? s1 : s0;
         A.partials = (double *)(base + L.off_part);
         A.tickets = (unsigned *)(base + L.off_tk);
@@ -631,13 +635,14 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
     init.kappa = 1.0;
     init.bhat = 1.0;
     init.last_check = INFINITY;
+    init.kpend = L.kpend;
     const int par0 = (int)(rounds_ & 1);
     net->round0 = rounds_;   // the network's first pass runs in the next round
     if (L.s == 4) {
         float *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (float *)(base + L.off_gT) + (size_t)k * n;
         ENG_TRY(launch_scale<float>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
-                                    (float *)(base + L.off_vec), (int64_t)(7 * n), st));
+                                    (float *)(base + L.off_vec), (int64_t)((5 + L.kpend) * n), st));
         fill_args<float>(h_tabf_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabf_ + 2 * slot, h_tabf_ + 2 * slot, 2 * sizeof(PassArgs<float>),
                                hipMemcpyHostToDevice, st));
@@ -645,7 +650,7 @@ int Engine::after_prepare(Net *net, hipStream_t st, std::string *err)
         double *gT[3] = {nullptr, nullptr, nullptr};
         for (int k = 0; k < p->dim; ++k) gT[k] = (double *)(base + L.off_gT) + (size_t)k * n;
         ENG_TRY(launch_scale<double>(lat, net->gd, (const uint8_t *)(base + L.off_mask), gT,
-                                     (double *)(base + L.off_vec), (int64_t)(7 * n), st));
+                                     (double *)(base + L.off_vec), (int64_t)((5 + L.kpend) * n), st));
         fill_args<double>(h_tabd_ + 2 * slot, net, par0, ds);
         ENG_TRY(hipMemcpyAsync(d_tabd_ + 2 * slot, h_tabd_ + 2 * slot, 2 * sizeof(PassArgs<double>),
                                hipMemcpyHostToDevice, st));

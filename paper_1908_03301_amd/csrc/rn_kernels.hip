@@ -142,10 +142,19 @@ __device__ __forceinline__ T apply_minv(T v, T d, bool jacobi) { return jacobi ?
 __device__ void step_after_cg(Scalars *s, const double *t)
 {
     const double pq = t[0], zq = t[1], qq = t[2], rz = t[3];
-    // a pass that left the FP64 field alone leaves the step before it pending
+    // a pass that left the FP64 field alone leaves the steps before it
+    // pending; once kpend are pending the next CG pass adds them all
     const bool flushed = s->flush != 0;
-    s->alpha2 = flushed ? 0.0 : s->alpha;
-    s->flush = flushed ? 0 : 1;
+    if (flushed) {
+        s->alpha2 = s->alpha3 = s->alpha4 = 0.0;
+        s->npend = 1;
+    } else {
+        s->alpha4 = s->alpha3;
+        s->alpha3 = s->alpha2;
+        s->alpha2 = s->alpha;
+        s->npend += 1;
+    }
+    s->flush = s->npend >= s->kpend ? 1 : 0;
     s->passes += 1;
     s->iters += 1;
     s->rho = rz;
@@ -193,8 +202,9 @@ __device__ void step_after_refresh(Scalars *s, const double *t)
     const double rr64 = t[0], rrs = t[1];
     s->passes += 1;
     s->refreshes += 1;
-    s->alpha2 = 0.0;                             // the refresh applied every pending step
+    s->alpha2 = s->alpha3 = s->alpha4 = 0.0;     // the refresh applied every pending step
     s->flush = 0;
+    s->npend = 1;                                // its own step is 0: counted as pending
     const double sigma_old = s->sigma;
     const double sigma = s->sigma_next;
     s->sigma = sigma;
@@ -373,27 +383,43 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
 }
 
 // What one pass does with the direction and the FP64 field, from the control
-// block: p1 holds p_{k-1}, whose step sa = sigma alpha is pending; p2 holds
-// p_{k-2}, whose step sa2 is also pending when the previous CG pass left the
-// field alone (then this CG pass flushes both); p0 receives p_k.
+// block: p1 holds p_{k-1}, whose step sa = sigma alpha is pending; p2, p3, p4
+// hold p_{k-2}, p_{k-3}, p_{k-4}, whose steps sa2, sa3, sa4 are also pending
+// while the CG passes after them left the field alone (a step not pending is
+// 0; a CG pass with `flush` adds them all); p0 receives p_k. A network keeps
+// up to kpend steps pending (4 for the FP32 2D passes, whose field update is
+// a phase of its own, else 2) in kpend + 1 buffers.
 template <typename T>
 struct Step {
-    const T *p1, *p2;
+    const T *p1, *p2, *p3, *p4;
     T *p0;
-    double sa, sa2;
+    double sa, sa2, sa3, sa4;
     bool flush;
 };
 
 template <typename T>
 __device__ __forceinline__ Step<T> make_step(const PassArgs<T> &a, const Scalars *s)
 {
-    const unsigned c = (unsigned)(s->passes % 3);
+    // the buffer of pass c - d: constant divisors and conditional wraps, not
+    // a 64-bit division by a runtime count at the start of every workgroup
+    const int nb = a.npbuf;
+    const int c = nb == 5 ? (int)(s->passes % 5) : (int)(s->passes % 3);
+    auto back = [&](int d) {
+        int v = c - d;
+        if (v < 0) v += nb;
+        if (v < 0) v += nb;
+        return v;
+    };
     Step<T> k;
-    k.p1 = a.pbuf[c == 0 ? 2 : c - 1];
-    k.p2 = a.pbuf[c == 2 ? 0 : c + 1];
     k.p0 = a.pbuf[c];
+    k.p1 = a.pbuf[back(1)];
+    k.p2 = a.pbuf[back(2)];
+    k.p3 = a.pbuf[back(3)];
+    k.p4 = a.pbuf[back(4)];
     k.sa = s->sigma * s->alpha;
     k.sa2 = s->sigma * s->alpha2;
+    k.sa3 = s->sigma * s->alpha3;
+    k.sa4 = s->sigma * s->alpha4;
     k.flush = s->flush != 0;
     return k;
 }
@@ -407,6 +433,8 @@ __device__ __forceinline__ double with_steps(double P, double sa2, double p2, do
     if (sa != 0.0) v = fma(sa, p1, v);
     return v;
 }
+
+
 
 // ---------------------------------------------------------------- refresh (FP64)
 // Node-local FP64 work of a refresh pass. The pending steps (sa p1, and
@@ -427,7 +455,7 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     const int c[3] = {x, y, z};
     const int n[3] = {a.nx, a.ny, a.nz};
     const int64_t st[3] = {sx, sy, sz};
-    const double sa = k_.sa, sa2 = k_.sa2;
+    const double sa = k_.sa, sa2 = k_.sa2, sa3 = k_.sa3, sa4 = k_.sa4;
     // neighbour j of the -k / +k bond (the node itself where there is none)
     int64_t jn[2 * DIM];
     bool has[2 * DIM];
@@ -458,13 +486,23 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
         return;
     }
     // batch 2: the node's and its neighbours' pressures and directions
-    const double Pi = ldc<COH>(Ps + i);
-    const T pi_ = ldc<COH>(k_.p1 + i), pi2_ = ldc<COH>(k_.p2 + i);
+    double Pi = ldc<COH>(Ps + i);
     double Pn[2 * DIM];
+#pragma unroll
+    for (int e = 0; e < 2 * DIM; ++e) Pn[e] = ldc<COH>(Ps + jn[e]);
+    // the steps before the last two, pending only with kpend 4 (the FP32 2D
+    // passes; a uniform branch, never on the first refresh): added first,
+    // oldest first, so that their directions are not held beside the others
+    if (DIM == 2 && sizeof(T) == 4 && (sa3 != 0.0 || sa4 != 0.0)) {
+        Pi = with_steps(Pi, sa4, (double)ldc<COH>(k_.p4 + i), sa3, (double)ldc<COH>(k_.p3 + i));
+#pragma unroll
+        for (int e = 0; e < 2 * DIM; ++e)
+            Pn[e] = with_steps(Pn[e], sa4, (double)ldc<COH>(k_.p4 + jn[e]), sa3, (double)ldc<COH>(k_.p3 + jn[e]));
+    }
+    const T pi_ = ldc<COH>(k_.p1 + i), pi2_ = ldc<COH>(k_.p2 + i);
     T pn_[2 * DIM], pn2_[2 * DIM];
 #pragma unroll
     for (int e = 0; e < 2 * DIM; ++e) {
-        Pn[e] = ldc<COH>(Ps + jn[e]);
         pn_[e] = ldc<COH>(k_.p1 + jn[e]);
         pn2_[e] = ldc<COH>(k_.p2 + jn[e]);
     }
@@ -583,14 +621,19 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     // (measured faster there).
     constexpr bool kFieldFirst = sizeof(T) == 4;
     if (kFieldFirst && flush) {
+        // up to four pending steps (kpend 4): the older two only when pending
+        const bool older = k.sa3 != 0.0 || k.sa4 != 0.0;
+        const T *__restrict__ p3s = k.p3;
+        const T *__restrict__ p4s = k.p4;
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int yy = y0 + j;
 #pragma unroll
             for (int sg = 0; sg < SEG; ++sg) {
                 const int64_t i = (int64_t)rowc(yy) * nx + xc[sg];
-                const double v = with_steps(ldc<COH>(P + i), k.sa2, (double)ldc<COH>(p2s + i), k.sa,
-                                            (double)ldc<COH>(ps + i));
+                double v = ldc<COH>(P + i);
+                if (older) v = with_steps(v, k.sa4, (double)ldc<COH>(p4s + i), k.sa3, (double)ldc<COH>(p3s + i));
+                v = with_steps(v, k.sa2, (double)ldc<COH>(p2s + i), k.sa, (double)ldc<COH>(ps + i));
                 if (valid[sg] && yy < ny) stc<COH>(P + i, v);
             }
         }
@@ -757,7 +800,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 // sums, ticket and control block, so networks advance independently and a
 // network's arithmetic does not depend on what else is in the launch.
 template <typename T, int SHAPE>
-__global__ __launch_bounds__(kBlock) void pass2d_kernel(const PassArgs<T> *__restrict__ tab,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void pass2d_kernel(const PassArgs<T> *__restrict__ tab,
                                                         const uint2 *__restrict__ blk, Scalars *scal, int parity,
                                                         int slot)
 {
@@ -1187,6 +1230,8 @@ __device__ __forceinline__ Scalars uniform_scalars(const Scalars *sv)
     u.sigma_next = rfl(sv->sigma_next);
     u.alpha = rfl(sv->alpha);
     u.alpha2 = rfl(sv->alpha2);
+    u.alpha3 = rfl(sv->alpha3);
+    u.alpha4 = rfl(sv->alpha4);
     u.beta = rfl(sv->beta);
     return u;
 }
@@ -1223,7 +1268,7 @@ __device__ __forceinline__ int my_xcd()
 // queue x (x = the workgroup's XCD with COH 2, else 0), and item it of queue x
 // is round it / n_x of entry xoff[x] + it % n_x.
 template <typename T, int SHAPE, int COH>
-__global__ __launch_bounds__(kBlock) void pass2d_persist(const PassArgs<T> *__restrict__ tab,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void pass2d_persist(const PassArgs<T> *__restrict__ tab,
                                                          const uint2 *__restrict__ blk, const int *__restrict__ xoff,
                                                          Scalars *scal, int64_t round_base, int rounds, int slot,
                                                          unsigned *err, unsigned long long *queues)
