@@ -523,6 +523,14 @@ def batch_bench(args, B, I, np):
     out["batch_wall_s"] = [round(w, 3) for w in walls_m]
     out["launch_shapes"] = shapes
     kern = kernel_accounting(B, nets, probs, steps_m, B.RN_MIXED, st_m)
+    if not kern:
+        # no per-launch times: pass rounds replayed from a hipGraph (RN_GRAPHS=1) record no events
+        out["roofline"] = None
+        out["roofline_note"] = "no per-launch device times: pass rounds were replayed from a hipGraph"
+        out["iters_mixed"] = {"median": int(np.median([r.iters for r in res_m])),
+                              "max": int(max(r.iters for r in res_m))}
+        ctx.close()
+        return out
     dom_key = max(kern, key=lambda k: kern[k]["device_s"])
     dom = kern[dom_key]
     traffic = traffic_from_profiles("batch512", dom_key)
