@@ -46,24 +46,95 @@ namespace rn {
 
 // ---------------------------------------------------------------- helpers
 
+// Lane moves inside a wave without the LDS crossbar. __shfl and its kin
+// compile to ds_bpermute, which takes an LDS instruction and a wait on the
+// lgkm counter per move; a DPP move is one VALU instruction and v_readlane
+// one more. lane_below(v): lane l receives lane l-1's v (whole-wave shift by
+// one, DPP wave_shr); lane_above(v): lane l receives lane l+1's v (wave_shl).
+// The lane at the wave's edge, which has no source, keeps its own v; every
+// caller overrides it. lane_bcast(v, l): lane l's v in every lane (l a
+// compile-time constant).
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __builtin_bit_cast(float, dpp_move<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = dpp_move<CTRL>((int)(b & 0xffffffffll)), hi = dpp_move<CTRL>((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T lane_below(T v) { return dpp_move<kDppWaveShr1>(v); }
+
+template <typename T>
+__device__ __forceinline__ T lane_above(T v) { return dpp_move<kDppWaveShl1>(v); }
+
+__device__ __forceinline__ float lane_bcast(float v, int l)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+__device__ __forceinline__ double lane_bcast(double v, int l)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane (every lane active):
+// pairs, then quads (DPP quad permutations), then eights and sixteens (DPP
+// half-row and row mirrors: lane i meets lane 7 - i, then 15 - i, so both
+// partners form the same sum), then the four row sums in a fixed order.
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E, kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_move<kDppQuadSwap1>(v);
+    v += dpp_move<kDppQuadSwap2>(v);
+    v += dpp_move<kDppRowHalfMirror>(v);
+    v += dpp_move<kDppRowMirror>(v);
+    return (lane_bcast(v, 0) + lane_bcast(v, 16)) + (lane_bcast(v, 32) + lane_bcast(v, 48));
 }
+
+// The CG state, the bonds and the field live in device memory: accesses
+// through these casts compile to global_load / global_store, which count on
+// the vector-memory counter only. Through a generic pointer (every pointer
+// read from an argument table is one) they are flat accesses, which count on
+// the lgkm counter as well, so each wait for an LDS read or a lane move would
+// also wait for every load and store still in flight.
+#define RN_GLOBAL __attribute__((address_space(1)))
+
+template <typename T>
+__device__ __forceinline__ T ldg(const T *p) { return *(const RN_GLOBAL T *)p; }
+
+template <typename T>
+__device__ __forceinline__ void stg(T *p, T v) { *(RN_GLOBAL T *)p = v; }
 
 // Partial sums travel between workgroups through write-through (system-scope)
 // stores and loads that bypass the per-XCD L2s, so no workgroup has to write
 // back or invalidate its L2 (a device-scope fence would do both).
 __device__ __forceinline__ double ld_through(const double *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return __hip_atomic_load((const RN_GLOBAL double *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void st_through(double *p, double v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store((RN_GLOBAL double *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Loads and stores of the CG state, by coherence mode:
@@ -83,18 +154,35 @@ __device__ __forceinline__ void st_through(double *p, double v)
 //     memory model lets workgroup scope hit L1); sc1 loads skip L1 and hit L2.
 // The bonds, the mask and the FP64 conductances are read-only during the
 // iterations and keep plain loads in every mode.
+// The same through a generic pointer (flat_load / flat_store): the 3D plane
+// stream below uses these; it measured faster with them (168.6 against 176.8
+// us per pass on a 256^3 network), the 2D tile slower.
 template <int COH, typename T>
-__device__ __forceinline__ T ldc(const T *p)
+__device__ __forceinline__ T ldc_flat(const T *p)
 {
     if constexpr (COH != 0) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else return *p;
 }
 
 template <int COH, typename T>
-__device__ __forceinline__ void stc(T *p, T v)
+__device__ __forceinline__ void stc_flat(T *p, T v)
 {
     if constexpr (COH == 1) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else *p = v;
+}
+
+template <int COH, typename T>
+__device__ __forceinline__ T ldc(const T *p)
+{
+    if constexpr (COH != 0) return __hip_atomic_load((const RN_GLOBAL T *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return ldg(p);
+}
+
+template <int COH, typename T>
+__device__ __forceinline__ void stc(T *p, T v)
+{
+    if constexpr (COH == 1) __hip_atomic_store((RN_GLOBAL T *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else stg(p, v);
 }
 
 // The memory scope of the reduction's own stores (partials, ticket resets,
@@ -327,12 +415,12 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
         // (s_waitcnt with every counter at 0), then count (device-scope
         // atomics, coherent across XCDs); groups is a power of two dividing grid
         __builtin_amdgcn_s_waitcnt(0);
-        const unsigned prev = __hip_atomic_fetch_add(tickets + (lb & (groups - 1)) * kStride, 1u,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add((RN_GLOBAL unsigned *)(tickets + (lb & (groups - 1)) * kStride),
+                                                     1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int last = prev == (unsigned)(grid / groups) - 1u;
         if (last && groups > 1) {
-            const unsigned top = __hip_atomic_fetch_add(tickets + groups * kStride, 1u, __ATOMIC_RELAXED,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned top = __hip_atomic_fetch_add((RN_GLOBAL unsigned *)(tickets + groups * kStride), 1u,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             last = top == (unsigned)groups - 1u;
         }
         is_last = last;
@@ -469,13 +557,13 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
         jn[2 * k + 1] = c[k] + 1 < n[k] ? i + st[k] : (wk ? i - span : i);
     }
     // batch 1: mask and bonds
-    const bool live = a.mask[i] == 3;
+    const bool live = ldg(a.mask + i) == 3;
     T gb[2 * DIM];
     double gd[2 * DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        const T gbm = a.gT[k][jn[2 * k]], gbp = a.gT[k][i];
-        const double gdm = a.g64[k][jn[2 * k]], gdp = a.g64[k][i];
+        const T gbm = ldg(a.gT[k] + jn[2 * k]), gbp = ldg(a.gT[k] + i);
+        const double gdm = ldg(a.g64[k] + jn[2 * k]), gdp = ldg(a.g64[k] + i);
         gb[2 * k] = has[2 * k] ? gbm : T(0);
         gb[2 * k + 1] = gbp;                     // 0 past the lattice edge
         gd[2 * k] = has[2 * k] ? gdm : 0.0;
@@ -651,8 +739,8 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             z_[sg][j] = ldc<COH>(zs + i);
             u_[sg][j] = ldc<COH>(us + i);
             p_[sg][j] = ldc<COH>(ps + i);
-            gxv[sg][j] = gx[i];
-            gyv[sg][j + 1] = gy[i];
+            gxv[sg][j] = ldg(gx + i);
+            gyv[sg][j + 1] = ldg(gy + i);
         }
     }
     double Pv[SEG][TY];
@@ -674,7 +762,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
         const int64_t ro = (int64_t)rowc(y0 - 1) * nx;
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
-            const T g0 = gy[ro + xc[sg]];
+            const T g0 = ldg(gy + ro + xc[sg]);
             gyv[sg][0] = below ? g0 : T(0);
         }
     }
@@ -705,7 +793,7 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
     T hz = T(0), hu = T(0), hp = T(0), hg = T(0);
     {
         const int64_t i = hok ? (int64_t)(y0 + hr_) * nx + hx : 0;
-        const T z0 = ldc<COH>(zs + i), u0 = ldc<COH>(us + i), p0 = ldc<COH>(ps + i), g0 = gx[i];
+        const T z0 = ldc<COH>(zs + i), u0 = ldc<COH>(us + i), p0 = ldc<COH>(ps + i), g0 = ldg(gx + i);
         if (hok) {
             hz = z0;
             hu = u0;
@@ -745,9 +833,9 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
     for (int j = 0; j < TY; ++j) {
         const int yy = y0 + j;
-        const T hl = __shfl(hpv, j, kWave);
-        const T hrr = __shfl(hpv, kWave - TY + j, kWave);
-        const T hgl = __shfl(hg, j, kWave);
+        const T hl = lane_bcast(hpv, j);
+        const T hrr = lane_bcast(hpv, kWave - TY + j);
+        const T hgl = lane_bcast(hg, j);
 #pragma unroll
         for (int sg = 0; sg < SEG; ++sg) {
             const int x = x0 + kWave * sg + lane;
@@ -756,12 +844,12 @@ __device__ __forceinline__ void cg2d_tile(const PassArgs<T> &a, double *__restri
             const T pc = pv[sg][j + 1];
             // neighbours across x: shuffles inside a segment, the neighbouring
             // segment's edge lane across a junction, the halo at the tile edges
-            T pl = __shfl_up(pc, 1, kWave);
-            T pr = __shfl_down(pc, 1, kWave);
-            T gxl = __shfl_up(gxv[sg][j], 1, kWave);
-            const T lj = sg == 0 ? hl : __shfl(pv[sg > 0 ? sg - 1 : 0][j + 1], kWave - 1, kWave);
-            const T gj = sg == 0 ? hgl : __shfl(gxv[sg > 0 ? sg - 1 : 0][j], kWave - 1, kWave);
-            const T rj = sg == SEG - 1 ? hrr : __shfl(pv[sg < SEG - 1 ? sg + 1 : 0][j + 1], 0, kWave);
+            T pl = lane_below(pc);
+            T pr = lane_above(pc);
+            T gxl = lane_below(gxv[sg][j]);
+            const T lj = sg == 0 ? hl : lane_bcast(pv[sg > 0 ? sg - 1 : 0][j + 1], kWave - 1);
+            const T gj = sg == 0 ? hgl : lane_bcast(gxv[sg > 0 ? sg - 1 : 0][j], kWave - 1);
+            const T rj = sg == SEG - 1 ? hrr : lane_bcast(pv[sg < SEG - 1 ? sg + 1 : 0][j + 1], 0);
             if (lane == 0) {
                 pl = lj;
                 gxl = gj;
@@ -954,23 +1042,23 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const int64_t i = rowoff[j] + zo;
-            R.z[j] = ldc<COH>(zs + i);
-            R.u[j] = ldc<COH>(us + i);
-            R.p[j] = ldc<COH>(ps + i);
+            R.z[j] = ldc_flat<COH>(zs + i);
+            R.u[j] = ldc_flat<COH>(us + i);
+            R.p[j] = ldc_flat<COH>(ps + i);
         }
         if (flush && ring) {           // a plane this tile stores: its FP64 field
 #pragma unroll
             for (int j = 0; j < kRows; ++j) {
                 const int64_t i = rowoff[j] + zo;
-                R.P[j] = ldc<COH>(P + i);
-                R.p2[j] = ldc<COH>(p2s + i);
+                R.P[j] = ldc_flat<COH>(P + i);
+                R.p2[j] = ldc_flat<COH>(p2s + i);
             }
         }
         if (ring) {
             const int64_t i = hoff + zo;
-            R.hz = ldc<COH>(zs + i);
-            R.hu = ldc<COH>(us + i);
-            R.hp = ldc<COH>(ps + i);
+            R.hz = ldc_flat<COH>(zs + i);
+            R.hu = ldc_flat<COH>(us + i);
+            R.hp = ldc_flat<COH>(ps + i);
         }
     };
     auto load_bonds = [&](Bond3<T> &G, int zz) {
@@ -978,11 +1066,11 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const int64_t i = rowoff[j] + zo;
-            G.x[j] = gx[i];
-            G.y[j] = gy[i];
-            G.z[j] = gz[i];
+            G.x[j] = ldc_flat<0>(gx + i);
+            G.y[j] = ldc_flat<0>(gy + i);
+            G.z[j] = ldc_flat<0>(gz + i);
         }
-        const T xh = gx[xhoff + zo], yh = gy[yhoff + zo];
+        const T xh = ldc_flat<0>(gx + xhoff + zo), yh = ldc_flat<0>(gy + yhoff + zo);
         G.xh = xhok ? xh : T(0);           // no bond left of x = 0
         G.yh = yhok ? yh : T(0);           // no bond below y = 0
     };
@@ -1005,7 +1093,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
         load_raw(R, z0, true);
         load_bonds(Gc, z0);
 #pragma unroll
-        for (int j = 0; j < kRows; ++j) gzm[j] = (in && rok[j]) ? gz[rowoff[j] + zc_(z0 - 1)] : T(0);
+        for (int j = 0; j < kRows; ++j) gzm[j] = (in && rok[j]) ? ldc_flat<0>(gz + rowoff[j] + zc_(z0 - 1)) : T(0);
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const bool ok = rok[j];
@@ -1014,8 +1102,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvc[j] = ok ? z_ : T(0);
             if (ok) {
                 const int64_t i = rowoff[j] + (int64_t)z0 * sz;
-                if (flush) stc<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
-                stc<COH>(zd + i, z_);
+                if (flush) stc_flat<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                stc_flat<COH>(zd + i, z_);
             }
             lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
         }
@@ -1037,8 +1125,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvn[j] = ok ? z_ : T(0);
             if (ok && nin) {
                 const int64_t i = rowoff[j] + (int64_t)zn * sz;
-                if (flush) stc<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
-                stc<COH>(zd + i, z_);
+                if (flush) stc_flat<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                stc_flat<COH>(zd + i, z_);
             }
             if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];
         }
@@ -1052,8 +1140,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
 #pragma unroll
         for (int j = 0; j < kRows; ++j) {
             const int ly = 1 + w * kRows + j;
-            T gxl = __shfl_up(Gc.x[j], 1, kWave);
-            const T gxh = __shfl(Gc.xh, j, kWave);
+            T gxl = lane_below(Gc.x[j]);
+            const T gxh = lane_bcast(Gc.xh, j);
             if (lane == 0) gxl = gxh;
             const T gyl = j == 0 ? Gc.yh : Gc.y[j - 1];
             const T p0 = pc[j];
@@ -1069,8 +1157,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             const T uv = live ? apply_minv(qv, d, jacobi) : T(0);
             if (rok[j]) {
                 const int64_t i = rowoff[j] + (int64_t)zc * sz;
-                stc<COH>(pd + i, p0);
-                stc<COH>(ud + i, uv);
+                stc_flat<COH>(pd + i, p0);
+                stc_flat<COH>(ud + i, uv);
             }
             const double dp = (double)p0, dq = (double)qv, du = (double)uv;
             const double dz = live ? (double)zvc[j] : 0.0;
