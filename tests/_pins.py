@@ -300,3 +300,17 @@ def bond_currents(net: Network, P: np.ndarray):
     occ = Gv > 0
     I, J, Gv = I[occ], J[occ], Gv[occ]
     return I, J, Gv, Gv * (p[I] - p[J])
+
+
+def prune_dangling(net: Network, mask: np.ndarray) -> Network:
+    """The network with every live node off the backbone cut out: each bond
+    with an end whose mask is 3 (live, not backbone: the oracle's backbone
+    mask marks backbone nodes 11) set to 0. Dangling ends carry no current,
+    so this leaves Q and K unchanged (pinned in test_oracle_backbone)."""
+    dangling = np.asarray(mask).reshape(net.shape) == 3
+    gp = [np.array(a, copy=True) for a in net.g]
+    for k in range(net.dim):
+        ax = net.dim - 1 - k
+        gp[k][dangling] = 0.0
+        gp[k][np.roll(dangling, -1, axis=ax)] = 0.0      # the entry of the neighbour below holds its bond
+    return Network(net.dim, net.nx, net.ny, net.nz, gp, net.axis, dict(net.meta), net.periodic)

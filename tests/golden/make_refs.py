@@ -14,13 +14,19 @@ so a file holds only the recipe and the results:
                       (which members, and the oracle's K for those whose
                       solve is affordable here)
   stream_refs.json    the same for 32 requests of the served stream
+  layered_refs.json   the 256^3 layered network at occupancy 0.27 (K_x and
+                      K_z), solved by the oracle with its dangling ends cut
+                      out (tests/_pins.prune_dangling on the oracle's
+                      backbone): the same K and, on the backbone, the same
+                      pressures, for 2.2 M unknowns instead of 8.5 M
 
-Usage: python3 tests/golden/make_refs.py [fullsize|batch|stream ...] [--jobs N]
+Usage: python3 tests/golden/make_refs.py [fullsize|batch|stream|layered ...] [--jobs N]
 (several hours of CPU in total, spread over N processes).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -59,6 +65,12 @@ FULLSIZE = {
                                              index=1304, axis=2)),
 }
 
+# the 256^3 layered network of the single-network workloads, flow along x and z
+LAYERED = {
+    "layered3d_256_x": ("stratified_network", dict(n=256, H=0.8, sigma=2.0, occupancy=0.27, index=0, axis=0)),
+    "layered3d_256_z": ("stratified_network", dict(n=256, H=0.8, sigma=2.0, occupancy=0.27, index=0, axis=2)),
+}
+
 BATCH_COUNT, STREAM_COUNT = 512, 512
 SAMPLE_MEMBERS = 32
 ORACLE_NODE_CAP = 1_100_000     # members above this many nodes get mask / residual checks only
@@ -81,6 +93,27 @@ def _fullsize_one(name):
            "energy": _pins.energy(net, r.pressure), "sample_index": [int(i) for i in pick],
            "sample_pressure": [float(v) for v in r.pressure.ravel()[pick]], "oracle_s": round(time.time() - t, 1)}
     print(f"{name}: K={r.K!r} iters={r.iters} live={r.n_live} in {out['oracle_s']}s", flush=True)
+    return name, out
+
+
+def _layered_one(name):
+    t = time.time()
+    net = make_network(LAYERED[name])
+    mask, n_live, n_bb = oracle.backbone(net)
+    pruned = _pins.prune_dangling(net, mask)
+    r = oracle.solve(pruned, tol=REF_TOL, want_mask=True)
+    bb = np.flatnonzero(r.mask.ravel() == 3)            # the pruned network's live set: the backbone
+    assert bb.size == n_bb
+    rng = np.random.default_rng([MASTER_SAMPLE_SEED, len(name)])
+    pick = np.sort(rng.choice(bb, size=min(SAMPLES, bb.size), replace=False))
+    R = _pins.face_path_resistance(net).ravel()[pick]     # on the whole network, as the GPU solves see it
+    out = {"recipe": list(LAYERED[name]), "status": r.status, "converged": bool(r.converged), "K": r.K, "G": r.G,
+           "Q_in": r.Q_in, "Q_out": r.Q_out, "rel_resid": r.rel_resid, "iters": r.iters, "n_live": n_live,
+           "n_backbone": n_bb, "backbone_mask_sha256": hashlib.sha256(np.ascontiguousarray(mask).tobytes()).hexdigest(),
+           "energy": _pins.energy(pruned, r.pressure), "sample_index": [int(i) for i in pick],
+           "sample_pressure": [float(v) for v in r.pressure.ravel()[pick]], "sample_R": [float(v) for v in R],
+           "oracle_s": round(time.time() - t, 1)}
+    print(f"{name}: K={r.K!r} iters={r.iters} live={n_live} backbone={n_bb} in {out['oracle_s']}s", flush=True)
     return name, out
 
 
@@ -114,7 +147,7 @@ def sample_members(kind):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", nargs="*", default=["fullsize", "batch", "stream"])
+    ap.add_argument("what", nargs="*", default=["fullsize", "batch", "stream", "layered"])
     ap.add_argument("--jobs", type=int, default=4)
     args = ap.parse_args()
     oracle.build(force=False)
@@ -123,6 +156,10 @@ def main():
             res = dict(ex.map(_fullsize_one, sorted(FULLSIZE)))
             doc = {"ref_tol": REF_TOL, "cases": res}
             json.dump(doc, open(os.path.join(HERE, "fullsize_refs.json"), "w"), indent=1)
+        if "layered" in args.what:
+            res = dict(ex.map(_layered_one, sorted(LAYERED)))
+            doc = {"ref_tol": REF_TOL, "cases": res}
+            json.dump(doc, open(os.path.join(HERE, "layered_refs.json"), "w"), indent=1)
         for kind in ("batch", "stream"):
             if kind not in args.what:
                 continue

@@ -11,7 +11,18 @@ flow along y and z, diluted near the threshold, device memory, nothing
 spanning and 2 planes on the flow axis (handled by the lattice path), a batch
 that mixes compact and lattice solves (each equal to the same solve alone),
 and the request server's rejection of the flag.
+
+At full size, the 256^3 layered network at occupancy 0.27 (flow along x and
+z) is solved on the lattice and with RN_OPT_BACKBONE | RN_OPT_COMPACT, both
+mixed, and held to tests/golden/layered_refs.json, written by
+tests/golden/make_refs.py from the oracle alone (its backbone, then its solve
+of the network with the dangling ends cut out, at 1e-13): K, the live and
+backbone counts, the backbone mask by its SHA-256, the energy floor and the
+pressures of 512 seeded backbone nodes within the energy bound.
 """
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -22,6 +33,8 @@ from paper_1908_03301_amd import inputs as I
 from tests import _pins
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 TOL = {B.RN_FP64: 1e-10, B.RN_MIXED: 1e-8}
 KBAR = {B.RN_FP64: 1e-9, B.RN_MIXED: 1e-7}
@@ -121,3 +134,40 @@ def test_compact_rejected_by_submit(ctx):
     net = I.iid_network(2, 64, 64, 1, occupancy=0.6, index=6150)
     with pytest.raises(B.RNError):
         ctx.submit(B.problem(net), B.opts(B.RN_MIXED, 1e-8, compact=True))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["layered3d_256_x", "layered3d_256_z"])
+def test_layered_256_against_oracle_refs(ctx, oracle_mod, name):
+    case = json.load(open(os.path.join(HERE, "golden", "layered_refs.json")))["cases"][name]
+    fn, kw = case["recipe"]
+    net = getattr(I, fn)(**kw)
+    assert case["converged"] and case["rel_resid"] <= 1e-13
+    idx, pref, R = (np.array(case[k]) for k in ("sample_index", "sample_pressure", "sample_R"))
+    c0 = None
+    for bb in (False, True):
+        say(f"{name} {'backbone+compact' if bb else 'lattice'} mixed")
+        r, P, M = B.solve_network(ctx, net, B.RN_MIXED, 1e-8, 2_000_000, want_pressure=True, want_mask=True,
+                                  backbone=bb, compact=bb)
+        say(f"{name}: K={r.K!r} ref={case['K']!r} iters={r.iters} live {r.n_live} backbone {r.n_backbone} "
+            f"loop {r.t_loop_s:.3f}s")
+        assert r.status == 0 and r.converged
+        assert r.n_live == case["n_live"]
+        if bb:
+            assert r.n_backbone == case["n_backbone"]
+            assert hashlib.sha256(np.ascontiguousarray(M).tobytes()).hexdigest() == case["backbone_mask_sha256"]
+        else:
+            c0 = (M & 7).copy()
+        assert r.K == pytest.approx(case["K"], rel=KBAR[B.RN_MIXED])
+        c = oracle_mod.check_pressure(net, P)
+        assert c.rel_resid <= 1.01 * TOL[B.RN_MIXED]
+        assert r.G == pytest.approx(c.G_E, rel=1e-9)
+        E = _pins.energy(net, P)
+        assert E >= case["energy"] * (1.0 - 1e-13), (E, case["energy"])
+        bound = _pins.pressure_error_bound(R, E, case["energy"])
+        err = np.abs(P.ravel()[idx] - pref)
+        worst = int(np.argmax(err / bound))
+        say(f"{name}: max |dP| {err.max():.3e}, energy excess {E - case['energy']:.3e}, "
+            f"worst err/bound {err[worst] / bound[worst]:.3f}")
+        assert np.all(err <= bound), (err[worst], bound[worst])
+    np.testing.assert_array_equal(M & 7, c0)               # the backbone solve's mask keeps the live bits

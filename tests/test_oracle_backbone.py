@@ -89,14 +89,8 @@ def test_backbone_carries_all_flow(oracle_mod, dim, shape, occ, periodic):
             assert Q > 0
             assert np.max(np.abs(cur[touches]), initial=0.0) <= 1e-12 * Q
         # remove every live node off the backbone: same flux, and the live set is the backbone
-        gp = [np.array(a, copy=True) for a in net.g]
-        for k in range(dim):
-            ax = dim - 1 - k
-            gk = gp[k]
-            off = dangling.reshape(net.shape)
-            gk[off] = 0.0
-            gk[np.roll(off, -1, axis=ax)] = 0.0     # the bond entry of the neighbour below
-        pruned = I.Network(dim, net.nx, net.ny, net.nz, gp, net.axis, periodic=periodic)
+        pruned = _pins.prune_dangling(net, m)
+        assert pruned.periodic == periodic and all(not np.shares_memory(a, b) for a, b in zip(pruned.g, net.g))
         P2, Q2 = _pins.dense_solve(pruned)
         assert Q2 == pytest.approx(Q, rel=1e-12, abs=1e-300)
         m2, nl2 = oracle_mod.mask_bfs(pruned)
