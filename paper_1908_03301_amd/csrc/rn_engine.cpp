@@ -302,7 +302,7 @@ Layout make_layout(const rn_problem *p, const rn_opts *o)
     L.off_P = take(16 * n);
     L.off_mask = take(n);
     L.off_gT = take((size_t)L.s * L.dim * n);
-    L.kpend = (L.dim == 2 && L.s == 4) ? 4 : 2;
+    L.kpend = L.s == 4 ? 4 : 2;
     // two sets of z and u and kpend + 1 directions; the labels of the
     // connectivity kernels (8 bytes per node) alias here
     L.off_vec = take((size_t)(5 + L.kpend) * L.s * n);

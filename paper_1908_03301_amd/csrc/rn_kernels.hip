@@ -475,8 +475,8 @@ __device__ void finish_pass(double (&acc)[kRed], double *partials, unsigned *tic
 // hold p_{k-2}, p_{k-3}, p_{k-4}, whose steps sa2, sa3, sa4 are also pending
 // while the CG passes after them left the field alone (a step not pending is
 // 0; a CG pass with `flush` adds them all); p0 receives p_k. A network keeps
-// up to kpend steps pending (4 for the FP32 2D passes, whose field update is
-// a phase of its own, else 2) in kpend + 1 buffers.
+// up to kpend steps pending (4 for the FP32 passes, 2 for the FP64 ones,
+// whose registers are scarcer) in kpend + 1 buffers.
 template <typename T>
 struct Step {
     const T *p1, *p2, *p3, *p4;
@@ -578,10 +578,10 @@ __device__ __forceinline__ void refresh_node(const PassArgs<T> &a, const double 
     double Pn[2 * DIM];
 #pragma unroll
     for (int e = 0; e < 2 * DIM; ++e) Pn[e] = ldc<COH>(Ps + jn[e]);
-    // the steps before the last two, pending only with kpend 4 (the FP32 2D
+    // the steps before the last two, pending only with kpend 4 (the FP32
     // passes; a uniform branch, never on the first refresh): added first,
     // oldest first, so that their directions are not held beside the others
-    if (DIM == 2 && sizeof(T) == 4 && (sa3 != 0.0 || sa4 != 0.0)) {
+    if (sizeof(T) == 4 && (sa3 != 0.0 || sa4 != 0.0)) {
         Pi = with_steps(Pi, sa4, (double)ldc<COH>(k_.p4 + i), sa3, (double)ldc<COH>(k_.p3 + i));
 #pragma unroll
         for (int e = 0; e < 2 * DIM; ++e)
@@ -957,7 +957,7 @@ constexpr int kRows = kTY / (kBlock / kWave);
 
 template <typename T>
 struct Raw3 {                  // one plane's loads for this thread
-    T z[kRows], u[kRows], p[kRows], p2[kRows];
+    T z[kRows], u[kRows], p[kRows], p2[kRows], p3[kRows], p4[kRows];
     double P[kRows];
     T hz, hu, hp;              // halo-ring node of this thread (if any)
 };
@@ -994,6 +994,8 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ us = a.src.u;
     const T *__restrict__ ps = k.p1;
     const T *__restrict__ p2s = k.p2;
+    const T *__restrict__ p3s = k.p3;
+    const T *__restrict__ p4s = k.p4;
     T *__restrict__ zd = a.dst.z;
     T *__restrict__ ud = a.dst.u;
     T *__restrict__ pd = k.p0;
@@ -1002,7 +1004,15 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
     const T *__restrict__ gz = a.gT[2];
     const bool flush = k.flush;        // uniform: this pass adds the pending steps to P
     const bool jacobi = a.jacobi != 0;
-    const double sa = k.sa, sa2 = k.sa2;
+    const double sa = k.sa, sa2 = k.sa2, sa3 = k.sa3, sa4 = k.sa4;
+    // up to four pending steps (kpend 4, FP32 only): the older two only when pending (uniform)
+    const bool older = sizeof(T) == 4 && flush && (sa3 != 0.0 || sa4 != 0.0);
+    // the FP64 field of a plane with every pending step added, oldest first
+    auto field = [&](const Raw3<T> &R, int j) {
+        double v = R.P[j];
+        if (older) v = with_steps(v, sa4, (double)R.p4[j], sa3, (double)R.p3[j]);
+        return with_steps(v, sa2, (double)R.p2[j], sa, (double)R.p[j]);
+    };
     const int yw = y0 + w * kRows;                 // first row of this wave
     bool rok[kRows], lok[kRows];                   // lattice node / slot holding a node or an image
     int64_t rowoff[kRows];                         // clamped x + sy * y of each row
@@ -1053,6 +1063,14 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
                 R.P[j] = ldc_flat<COH>(P + i);
                 R.p2[j] = ldc_flat<COH>(p2s + i);
             }
+            if (older) {
+#pragma unroll
+                for (int j = 0; j < kRows; ++j) {
+                    const int64_t i = rowoff[j] + zo;
+                    R.p3[j] = ldc_flat<COH>(p3s + i);
+                    R.p4[j] = ldc_flat<COH>(p4s + i);
+                }
+            }
         }
         if (ring) {
             const int64_t i = hoff + zo;
@@ -1102,7 +1120,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvc[j] = ok ? z_ : T(0);
             if (ok) {
                 const int64_t i = rowoff[j] + (int64_t)z0 * sz;
-                if (flush) stc_flat<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                if (flush) stc_flat<COH>(P + i, field(R, j));
                 stc_flat<COH>(zd + i, z_);
             }
             lp[z0 % 3][1 + w * kRows + j][1 + lane] = pc[j];
@@ -1125,7 +1143,7 @@ __device__ __forceinline__ void cg3d_tile(const PassArgs<T> &a, double *__restri
             zvn[j] = ok ? z_ : T(0);
             if (ok && nin) {
                 const int64_t i = rowoff[j] + (int64_t)zn * sz;
-                if (flush) stc_flat<COH>(P + i, with_steps(R.P[j], sa2, (double)R.p2[j], sa, (double)R.p[j]));
+                if (flush) stc_flat<COH>(P + i, field(R, j));
                 stc_flat<COH>(zd + i, z_);
             }
             if (nin) lp[zn % 3][1 + w * kRows + j][1 + lane] = pn[j];

@@ -57,7 +57,7 @@ struct Layout {
     bool copy_g = false;
     int grid = 8, groups = 1, tpw = 1, ntx = 1, nty = 1, ntz = 1, ntiles = 1, tile_z = 16;
     int shape = 0;   // 2D tile: 0 full, 1 small
-    int kpend = 2;   // CG steps the FP64 field may fall behind (4 for FP32 2D, whose update is its own phase)
+    int kpend = 2;   // CG steps the FP64 field may fall behind (4 with FP32 vectors, 2 with FP64)
     size_t off_g64 = 0, off_P = 0, off_mask = 0, off_gT = 0, off_vec = 0,
            off_part = 0, off_tk = 0, off_cnt = 0, total = 0;
 };
