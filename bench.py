@@ -69,7 +69,7 @@ def pass_bytes(dim: int, n: int, s: int, live: int) -> dict:
 
     CG pass: a live node reads z, p, u and dim conductance arrays (s bytes
     each) and writes z, p, u: (dim + 6) s bytes; its Jacobi diagonal is the
-    sum of the bonds it reads. One CG pass in kpend (4 for FP32 2D, else 2)
+    sum of the bonds it reads. One CG pass in kpend (4 for FP32, 2 for FP64)
     also reads the directions of the kpend - 1 passes before ((kpend - 1) s)
     and reads and writes the FP64 pressure (16): the figure is the average
     over kpend passes. Refresh pass: every node copies its FP64 pressure (16
@@ -77,7 +77,7 @@ def pass_bytes(dim: int, n: int, s: int, live: int) -> dict:
     reads dim FP64 conductances and two directions and writes z, p, u:
     8 dim + 5 s bytes more.
     """
-    kp = 4 if (dim == 2 and s == 4) else 2
+    kp = 4 if s == 4 else 2
     return {"cg": ((dim + 6) * s * kp + 16 + (kp - 1) * s) * live // kp,
             "refresh": (16 + dim * s) * n + (8 * dim + 5 * s) * live}
 
